@@ -1,0 +1,30 @@
+"""FP64 CPU oracle for the explicit upwind DG elastic-wave right-hand side.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The HIP library and
+its Python binding never import it, and this package imports nothing from
+them: the two share no kernels, helpers, tables or constants.
+
+The oracle is written for clarity, not speed: a modal Galerkin method with an
+orthonormal basis of P_N built by Cholesky orthonormalisation of Legendre
+products, every integral evaluated by quadrature, faces matched by physical
+coordinates.  The GPU path instead uses a nodal basis, derivative/lift
+matrices and topological face permutations.  Both discretise the same
+semi-discrete operator, which does not depend on the basis:
+
+* the first-order system  sum_k d_k(A_k u) + C u = f  (Sec. 2, eq. LPDE) with
+  the elastic velocity-strain instance (C = 0);
+* the upwind HDG flux  F^.n = F(u).n + |A|(u - u^)  (Sec. 2, eq.
+  RiemannFluxBoth) with the trace u^ eliminated through the single-valued
+  trace condition (Sec. 2, eq. HDGeqn; Sec. 3, eq. iHDGtrace), generalised
+  to different impedances on the two sides of a face;
+* the element-by-element explicit update of Sec. 4.3 with forward Euler
+  replaced by a five-stage low-storage Runge-Kutta scheme.
+
+Parity status: every function is pinned by tests under tests/ (exactness,
+closed-form energy rate, conservation, plane-wave convergence, symmetry,
+Runge-Kutta order conditions).  Absolute solution values of the large
+heterogeneous workloads are not printed in the paper and are pinned only
+through those properties.
+"""
+
