@@ -1,0 +1,170 @@
+"""Throughput benchmark of the fused DG right-hand side + LSRK(5,4) step.
+
+Workload (default): heterogeneous periodic cube [-1,1]^3 of 32^3 hexahedra x 6
+= 196,608 tetrahedra, degree N=4 (35 nodes), 9 fields, smooth rho, lambda,
+mu sampled at the quadrature points, Ricker point source (f0=5), time step
+at CFL 0.5.  One "step" is one LSRK(5,4) step, i.e. five fused stage
+launches over the whole mesh.  Inputs are resident in HBM before timing.
+
+Prints one JSON line.  GDOF/s counts K*Np*9 degrees of freedom per RHS
+evaluation (five per step).  The FP32 run is the headline value; the FP64
+run and the FP64 CPU oracle (timed on a bounded sample) are reported beside
+it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DG RHS GDOF/s at N=4, FP32 vs FP64 vs oracle; batched solve p50/p99 latency"
+
+
+def algorithmic_bytes_per_element(Np, Nq, b):
+    """Compulsory HBM bytes per element per stage: q and the LSRK register
+    read and written (36 Np b), the density-weighted mass inverse (Np^2 b),
+    lambda and mu at the quadrature points (2 Nq b), geometry (26 b) and
+    connectivity (48 B)."""
+    return 36 * Np * b + Np * Np * b + 2 * Nq * b + 26 * b + 48
+
+
+def build_workload(n, N):
+    from workloads import media
+    from workloads.mesh import kuhn_periodic_mesh
+    EToV, VXYZ = kuhn_periodic_mesh(n)
+    return EToV, VXYZ, media
+
+
+def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ):
+    import torch
+
+    import paper_1711_01175_amd as P
+    from workloads import media
+    stream = torch.cuda.current_stream()
+    c = P.Context(N, prec, stream=stream.cuda_stream)
+    c.set_mesh(EToV, VXYZ)
+    c.bind_workspace()
+    xyz = c.quadrature_points()
+    rho, lam, mu = media.smooth(xyz)
+    del xyz
+    c.set_material(rho, lam, mu)
+    c.set_source([0.05, -0.10, 0.15], [0.0, 0.0, 1.0], 1.0, 5.0, 0.2)
+    dt = c.cfl_dt(0.5)
+    c.set_state(torch.zeros((c.K, 9, c.Np), dtype=c.torch_dtype, device="cuda"), 0.0)
+    c.step(dt, warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    c.step(dt, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    energy = c.energy()
+    out = dict(K=c.K, Np=c.Np, Nq=c.Nq, dt=dt, ms=ms, energy=energy, t=c.time())
+    c.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(N, n_sample, seconds):
+    """Time the FP64 oracle's RHS on a smaller mesh of the same workload
+    (per-element work does not depend on the mesh size)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle.dg import Elastic
+    from oracle.reference import stroud_rule
+    from workloads import media
+    from workloads.mesh import kuhn_periodic_mesh
+    EToV, VXYZ = kuhn_periodic_mesh(n_sample)
+    xq, _ = stroud_rule(N)
+    X0 = VXYZ[:, 0]
+    A = np.stack([VXYZ[:, 1] - X0, VXYZ[:, 2] - X0, VXYZ[:, 3] - X0], axis=-1) / 2.0
+    xyz = np.einsum('qd,kjd->kqj', xq + 1.0, A) + X0[:, None, :]
+    op = Elastic(N, VXYZ, *media.smooth(xyz))
+    c = np.random.default_rng(0).standard_normal((op.K, 9, op.Np))
+    op.rhs(c)
+    calls, t0 = 0, time.perf_counter()
+    while True:
+        op.rhs(c)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    gdofs = op.K * op.Np * 9 * calls / el / 1e9
+    return dict(value=gdofs, unit="GDOF/s", cores=int(threads), kind="oracle",
+                sample=f"{calls} RHS evaluations of the FP64 oracle on the same workload "
+                       f"(N={N}, same media) restricted to a {n_sample}^3 x 6 = {op.K}-element mesh, "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=32, help="hexahedra per axis")
+    ap.add_argument("--N", type=int, default=4, help="polynomial degree")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-n", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(how the path would shard is described in the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    EToV, VXYZ, _ = build_workload(args.n, args.N)
+    r32 = run_gpu(32, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)
+    r64 = None if args.skip_fp64 else run_gpu(64, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)
+    K, Np, Nq = r32["K"], r32["Np"], r32["Nq"]
+    dof = K * Np * 9
+    g32 = dof * 5 * args.steps / (r32["ms"] * 1e-3) / 1e9
+    stage_s = r32["ms"] * 1e-3 / (5 * args.steps)
+    algo = algorithmic_bytes_per_element(Np, Nq, 4) * K
+    achieved = algo / stage_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(g32, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"heterogeneous periodic cube {args.n}^3 hexes x 6 = {K} tets, N={args.N} "
+                               f"({Np} nodes), 9 fields, smooth rho/lambda/mu at quadrature nodes, "
+                               f"Ricker f0=5, LSRK(5,4) at CFL 0.5",
+                   "K": K, "N": args.N, "Np": Np, "dt": r32["dt"], "dof_per_stage": dof},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_stage (fused stage)", "stage_us": round(stage_s * 1e6, 2),
+                     "algorithmic_bytes_per_stage": algo},
+    }
+    if r64 is not None:
+        g64 = dof * 5 * args.steps / (r64["ms"] * 1e-3) / 1e9
+        st64 = r64["ms"] * 1e-3 / (5 * args.steps)
+        a64 = algorithmic_bytes_per_element(Np, Nq, 8) * K / st64 / 1e9
+        line["fp64"] = {"value": round(g64, 3), "unit": "GDOF/s", "ms_per_step": round(r64["ms"] / args.steps, 4),
+                        "roofline_frac": round(a64 / HBM_PEAK_GBS, 4), "achieved_GBs": round(a64, 1)}
+        line["fp32_vs_fp64_speedup"] = round(r64["ms"] / r32["ms"], 3)
+        line["energy_fp32_fp64"] = [r32["energy"], r64["energy"]]
+    if args.cpu_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(args.N, args.cpu_n, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * ewdg -- explicit upwind nodal DG for the velocity-strain elastic wave
+ * equation on periodic tetrahedral meshes, one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed.  The semi-discrete operator L(q) of the first-order
+ * system sum_k d_k(A_k u) + C u = f (Sec. 2, eq. LPDE) in its elastic
+ * velocity-strain instance (C = 0):
+ *     rho dv/dt = div(sigma) + f,  de/dt = sym(grad v),
+ *     sigma = lambda tr(e) I + 2 mu e,
+ * discretised element by element with the upwind HDG flux
+ * F^.n = F(u).n + |A|(u - u^) (Sec. 2, eq. RiemannFluxBoth) whose trace u^
+ * is eliminated through the single-valued flux condition (Sec. 2, eq.
+ * HDGeqn; Sec. 3, eq. iHDGtrace with equal iterates).  With different
+ * impedances on the two sides of a face the exact Riemann state per wave
+ * mode is used; it reduces to that flux when the material is continuous.
+ * Time stepping is the element-by-element explicit update of Sec. 4.3 with
+ * forward Euler replaced by Carpenter-Kennedy LSRK(5,4).
+ *
+ * Discretisation details fixed by this interface:
+ *  - unknowns per element: q = (v_x, v_y, v_z, e_xx, e_yy, e_zz, e_yz, e_xz,
+ *    e_xy) with tensor shear strains; each field is a degree-N polynomial
+ *    stored at Np = (N+1)(N+2)(N+3)/6 nodes (warp & blend nodes);
+ *  - state layout q[K][9][Np], element-major, in the context's precision;
+ *  - reference element T = {r,s,t >= -1, r+s+t <= -1} with vertices
+ *    v0=(-1,-1,-1), v1=(1,-1,-1), v2=(-1,1,-1), v3=(-1,-1,1); element k is
+ *    the affine image sending v_i to its i-th vertex;
+ *  - quadrature Q_N: Stroud conical product, (N+1)^3 points, Gauss-Jacobi
+ *    weights (1-x)^0,(1-x)^1,(1-x)^2 in the collapsed directions a, b, c
+ *    with r = (1+a)(1-b)(1-c)/4 - 1, s = (1+b)(1-c)/2 - 1, t = c; point
+ *    index q = i + (N+1)(j + (N+1)k) for (a_i, b_j, c_k).  Material fields
+ *    are sampled at these points ([K][Nq]) and define the density-weighted
+ *    mass and the stress projection sigma_h = P_Q(lambda tr(e) I + 2 mu e);
+ *  - impedances Z_p = sqrt(rho(lambda+2mu)), Z_s = sqrt(rho mu) from the
+ *    quadrature-weighted element means.
+ *
+ * Conventions.  Every function returns an int status (EWDG_OK = 0 or a
+ * negative EWDG_E* code) and never throws.  ewdg_last_error(ctx) returns a
+ * message owned by the context, valid until its next call.  A context is
+ * not thread-safe; distinct contexts are independent.  All device work is
+ * enqueued on the context's HIP stream; functions returning host data
+ * synchronise that stream.  Host input arrays are borrowed for the call and
+ * copied.  Device memory is owned by the caller: the library works inside
+ * one caller-allocated workspace (ewdg_workspace_bytes / ewdg_bind_workspace)
+ * and never allocates device memory itself.
+ */
+#ifndef EWDG_H
+#define EWDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  EWDG_OK = 0,
+  EWDG_EINVAL = -1, /* bad argument, shape or unsupported degree            */
+  EWDG_ESTATE = -2, /* call order (e.g. step before material)               */
+  EWDG_ENOMEM = -3, /* workspace or receiver capacity too small             */
+  EWDG_EHIP = -4,   /* HIP runtime error                                    */
+  EWDG_EMESH = -5,  /* unmatched face, J <= 0, non-conforming mesh          */
+  EWDG_EPOINT = -6  /* source or receiver outside the mesh                  */
+};
+
+typedef struct ewdg_ctx ewdg_ctx;
+
+/* Create a context for degree N (1..5 or 7) and precision 32 or 64 bits.
+ * hip_stream is a hipStream_t (NULL = default stream).  Builds the
+ * reference element on the host; touches no GPU state. */
+int ewdg_create(int N, int precision_bits, void* hip_stream, ewdg_ctx** out);
+int ewdg_destroy(ewdg_ctx* ctx);
+int ewdg_set_stream(ewdg_ctx* ctx, void* hip_stream);
+
+/* Mesh (Sec. 2: elements, skeleton, outward normals).  EToV[K][4] holds
+ * vertex ids with periodic images identified; VXYZ[K][4][3] holds each
+ * element's own (unwrapped) vertex coordinates.  Every face must be shared
+ * with exactly one other element (EWDG_EMESH otherwise), every element must
+ * have positive orientation.  Host arrays. */
+int ewdg_set_mesh(ewdg_ctx* ctx, int64_t K, const int64_t* EToV, const double* VXYZ);
+
+/* Sizes of one element: nodes, face nodes, quadrature points. */
+int ewdg_sizes(const ewdg_ctx* ctx, int* Np, int* Nfp, int* Nq);
+/* Physical node and quadrature-point coordinates, host [K][Np][3] / [K][Nq][3]. */
+int ewdg_node_points(const ewdg_ctx* ctx, double* xyz);
+int ewdg_quadrature_points(const ewdg_ctx* ctx, double* xyz);
+/* Reference-element operators (host, FP64, row-major) for inspection:
+ * which = 0 Dr, 1 Ds, 2 Dt [Np][Np]; 3 LIFT [Np][4Nfp]; 4 Vq [Nq][Np];
+ * 5 Pq [Np][Nq]; 6 reference mass [Np][Np]; 7 nodes (r,s,t) [Np][3];
+ * 8 quadrature weights [Nq]. */
+int ewdg_reference_operator(const ewdg_ctx* ctx, int which, double* out);
+
+/* Device workspace needed for the mesh plus up to max_receivers receivers
+ * recorded over up to max_record_steps steps.  Requires the mesh. */
+int ewdg_workspace_bytes(const ewdg_ctx* ctx, int max_receivers, int max_record_steps,
+                         size_t* bytes);
+/* Bind caller-owned device memory of at least
+ * ewdg_workspace_bytes(ctx, max_receivers, max_record_steps) bytes,
+ * 256-byte aligned (EWDG_ENOMEM if too small).  Uploads the mesh tables and
+ * reference operators; synchronises.  The memory must stay valid until the
+ * context is destroyed or rebound. */
+int ewdg_bind_workspace(ewdg_ctx* ctx, void* device_ptr, size_t bytes, int max_receivers,
+                        int max_record_steps);
+
+/* Material at the quadrature points, host FP64 [K][Nq] each; rho, mu > 0,
+ * lambda >= 0.  Builds on the GPU, in FP64, the per-element density-
+ * weighted mass inverse W_rho = M_rho^-1 M (stored in run precision), the
+ * impedances, and run-precision copies of lambda and mu.  Resets the state
+ * to zero at t = 0. */
+int ewdg_set_material(ewdg_ctx* ctx, const double* rho_q, const double* lam_q,
+                      const double* mu_q);
+
+/* State in the public nodal layout q[K][9][Np] of the context precision;
+ * on_device selects device (1) or host (0) memory. */
+int ewdg_set_state(ewdg_ctx* ctx, const void* q, int on_device, double t);
+int ewdg_get_state(ewdg_ctx* ctx, void* q, int on_device, double* t);
+/* L2 projection under Q_N of values at the quadrature points:
+ * fq_dev [K][9][Nq] FP64 (device) -> q_dev [K][9][Np] context precision. */
+int ewdg_project_quadrature(ewdg_ctx* ctx, const double* fq_dev, void* q_dev);
+/* Evaluate a nodal field at the quadrature points (FP64 arithmetic):
+ * q_dev [K][9][Np] (NULL = current state) -> fq_dev [K][9][Nq] FP64. */
+int ewdg_eval_quadrature(ewdg_ctx* ctx, const void* q_dev, double* fq_dev);
+
+/* Point force amp * R(t) * dir at xs with the Ricker wavelet
+ * R(t) = (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2).  The owning
+ * element is the lowest-index element containing xs (EWDG_EPOINT if none). */
+int ewdg_set_source(ewdg_ctx* ctx, const double xs[3], const double dir[3], double amp,
+                    double f0, double t0);
+int ewdg_clear_source(ewdg_ctx* ctx);
+/* Receivers: v at nr points (host [nr][3]) recorded in FP64 after every
+ * full step; recording restarts at zero. */
+int ewdg_set_receivers(ewdg_ctx* ctx, int nr, const double* xr);
+/* Copy the recorded traces to host out[nsteps][nr][3]; *nsteps receives
+ * the number of recorded steps (out may be NULL to query it). */
+int ewdg_receivers(ewdg_ctx* ctx, double* out, int* nsteps);
+
+/* dt = cfl * min_K (r_K / max_q c_p) / (N+1)^2 (explicit step scaling
+ * h/(p^2 c) of Sec. 4.4); r_K the inradius. */
+int ewdg_cfl_dt(const ewdg_ctx* ctx, double cfl, double* dt);
+
+/* One evaluation rhs = L(q) + source at time t, device arrays [K][9][Np]
+ * in the context precision.  Does not change the stored state. */
+int ewdg_rhs(ewdg_ctx* ctx, double t, const void* q_dev, void* rhs_dev);
+/* Advance the stored state by nsteps LSRK(5,4) steps of size dt,
+ * recording receivers after each step. */
+int ewdg_step(ewdg_ctx* ctx, double dt, int nsteps);
+/* Current simulation time. */
+int ewdg_time(const ewdg_ctx* ctx, double* t);
+/* E = 1/2 (rho v, v)_Q + 1/2 sum_K J sum_q w e:sigma, accumulated in FP64
+ * with a deterministic reduction; synchronises. */
+int ewdg_energy(ewdg_ctx* ctx, double* E);
+
+const char* ewdg_last_error(const ewdg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EWDG_H */

@@ -1,0 +1,564 @@
+// C-ABI entry points: context lifecycle, workspace layout, uploads and the
+// LSRK(5,4) driver.  Device work is enqueued on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dev.hpp"
+#include "ewdg.h"
+#include "mesh.hpp"
+#include "refelem.hpp"
+
+using namespace ewdg;
+
+namespace {
+
+// Carpenter-Kennedy (5,4) 2N-storage coefficients (NASA TM-109112).
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+const double kRkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                        2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+double ricker(double t, double f0, double t0) {
+  const double a = (M_PI * f0 * (t - t0)) * (M_PI * f0 * (t - t0));
+  return (1.0 - 2.0 * a) * std::exp(-a);
+}
+
+}  // namespace
+
+struct ewdg_ctx {
+  int N = 0, prec = 0;
+  hipStream_t stream = nullptr;
+  RefElem re;
+  MeshData mesh;
+  bool has_mesh = false, bound = false, has_material = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int max_rec = 0, max_steps = 0;
+  Dev d;
+  int cur = 0;
+  double t = 0.0;
+  std::vector<double> cpmax;  // per element max_q c_p
+  bool has_source = false;
+  int64_t src_elem = -1;
+  double src_dir[3] = {0, 0, 0}, src_amp = 0, src_f0 = 0, src_t0 = 0;
+  int nr = 0, rec_count = 0;
+  std::string err;
+
+  size_t tsz() const { return prec == 32 ? 4 : 8; }
+  int fail(int code, const std::string& m) {
+    err = m;
+    return code;
+  }
+  int hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return EWDG_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return EWDG_EHIP;
+  }
+};
+
+namespace {
+
+// Sequential 256-byte aligned layout of the workspace.  With base == nullptr
+// only the total size is computed.
+size_t layout(ewdg_ctx* c, char* base) {
+  const int64_t K = c->mesh.K;
+  const size_t Np = c->re.Np, Nfp = c->re.Nfp, Nq = c->re.Nq, ts = c->tsz();
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  Dev& d = c->d;
+  d.q[0] = take(9 * Np * K * ts);
+  d.s[0] = take(6 * Np * K * ts);
+  char* scratch = base ? base + off : nullptr;
+  const size_t scratch_begin = off;
+  d.q[1] = take(9 * Np * K * ts);
+  d.s[1] = take(6 * Np * K * ts);
+  d.res = take(9 * Np * K * ts);
+  d.scratch = scratch;
+  d.scratch_bytes = off - scratch_begin;
+  d.W = take(Np * Np * K * ts);
+  d.lm = take(2 * Nq * K * ts);
+  d.geo = take(9 * K * ts);
+  d.fgeo = take(16 * K * ts);
+  d.Z = take(2 * K * ts);
+  d.svec = take(Np * ts);
+  d.DrT = take(Np * Np * ts);
+  d.DsT = take(Np * Np * ts);
+  d.DtT = take(Np * Np * ts);
+  d.LIFTT = take(4 * Nfp * Np * ts);
+  d.VqT = take(Nq * Np * ts);
+  d.PqT = take(Nq * Np * ts);
+  d.Vq64T = reinterpret_cast<double*>(take(Nq * Np * 8));
+  d.Pq64T = reinterpret_cast<double*>(take(Nq * Np * 8));
+  d.Mhat64 = reinterpret_cast<double*>(take(Np * Np * 8));
+  d.wq64 = reinterpret_cast<double*>(take(Nq * 8));
+  d.rho64 = reinterpret_cast<double*>(take(Nq * K * 8));
+  d.lam64 = reinterpret_cast<double*>(take(Nq * K * 8));
+  d.mu64 = reinterpret_cast<double*>(take(Nq * K * 8));
+  d.J64 = reinterpret_cast<double*>(take(K * 8));
+  d.epart = reinterpret_cast<double*>(take(K * 8));
+  d.scal = reinterpret_cast<double*>(take(64 * 8));
+  d.srcb = reinterpret_cast<double*>(take(Np * 8));
+  d.msmall = reinterpret_cast<double*>(take(Np * Np * 8));
+  const size_t mr = c->max_rec > 0 ? c->max_rec : 1, ms = c->max_steps > 0 ? c->max_steps : 1;
+  d.rec_rows = reinterpret_cast<double*>(take(mr * Np * 8));
+  d.rec_elem = reinterpret_cast<int32_t*>(take(mr * 4));
+  d.rec_out = reinterpret_cast<double*>(take(ms * mr * 3 * 8));
+  d.conn = reinterpret_cast<int32_t*>(take(4 * K * 4));
+  d.nbrnode = reinterpret_cast<int32_t*>(take(96 * Nfp * 4));
+  d.fmask = reinterpret_cast<int32_t*>(take(4 * Nfp * 4));
+  return off;
+}
+
+template <typename T>
+std::vector<T> convert(const std::vector<double>& v) {
+  std::vector<T> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = static_cast<T>(v[i]);
+  return o;
+}
+
+std::vector<double> transpose(const std::vector<double>& A, int rows, int cols) {
+  std::vector<double> B(A.size());
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) B[static_cast<size_t>(j) * rows + i] = A[static_cast<size_t>(i) * cols + j];
+  return B;
+}
+
+int upload_run(ewdg_ctx* c, void* dst, const std::vector<double>& src) {
+  if (int rc = c->hip(hipStreamSynchronize(c->stream), "upload sync")) return rc;
+  if (c->prec == 32) {
+    const std::vector<float> f = convert<float>(src);
+    return c->hip(hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice), "upload");
+  }
+  return c->hip(hipMemcpy(dst, src.data(), src.size() * 8, hipMemcpyHostToDevice), "upload");
+}
+
+int upload(ewdg_ctx* c, void* dst, const void* src, size_t bytes) {
+  // device work already queued on the context stream may still read dst
+  if (int rc = c->hip(hipStreamSynchronize(c->stream), "upload sync")) return rc;
+  return c->hip(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "upload");
+}
+
+// Nodal basis values l_i(rhat) = sum_m psi_m(rhat) Vinv[m][i].
+std::vector<double> nodal_row(const RefElem& re, const double* rh) {
+  std::vector<double> psi(re.Np);
+  pkdo_eval(re.N, rh[0], rh[1], rh[2], psi.data(), nullptr, nullptr, nullptr);
+  std::vector<double> row(re.Np, 0.0);
+  for (int i = 0; i < re.Np; ++i)
+    for (int m = 0; m < re.Np; ++m) row[i] += psi[m] * re.Vinv[m * re.Np + i];
+  return row;
+}
+
+int need(const ewdg_ctx* c, bool mesh, bool bound, bool material) {
+  if (!c) return EWDG_EINVAL;
+  if (mesh && !c->has_mesh) return EWDG_ESTATE;
+  if (bound && !c->bound) return EWDG_ESTATE;
+  if (material && !c->has_material) return EWDG_ESTATE;
+  return EWDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ewdg_create(int N, int precision_bits, void* hip_stream, ewdg_ctx** out) {
+  if (!out) return EWDG_EINVAL;
+  *out = nullptr;
+  if (!supported_degree(N) || (precision_bits != 32 && precision_bits != 64)) return EWDG_EINVAL;
+  ewdg_ctx* c = new (std::nothrow) ewdg_ctx();
+  if (!c) return EWDG_ENOMEM;
+  c->N = N;
+  c->prec = precision_bits;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  char msg[256] = {0};
+  if (!build_refelem(N, c->re, msg, sizeof(msg))) {
+    delete c;
+    return EWDG_EINVAL;
+  }
+  c->d.N = N;
+  c->d.prec = precision_bits;
+  c->d.Np = c->re.Np;
+  c->d.Nfp = c->re.Nfp;
+  c->d.Nq = c->re.Nq;
+  *out = c;
+  return EWDG_OK;
+}
+
+int ewdg_destroy(ewdg_ctx* c) {
+  delete c;
+  return EWDG_OK;
+}
+
+int ewdg_set_stream(ewdg_ctx* c, void* s) {
+  if (!c) return EWDG_EINVAL;
+  c->stream = static_cast<hipStream_t>(s);
+  return EWDG_OK;
+}
+
+const char* ewdg_last_error(const ewdg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int ewdg_set_mesh(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* VXYZ) {
+  if (!c || !EToV || !VXYZ) return EWDG_EINVAL;
+  MeshData m;
+  std::string e;
+  const int rc = build_mesh(K, EToV, VXYZ, m, e);
+  if (rc != EWDG_OK) return c->fail(rc, e);
+  c->mesh = std::move(m);
+  c->has_mesh = true;
+  c->bound = false;
+  c->has_material = false;
+  c->d.K = K;
+  return EWDG_OK;
+}
+
+int ewdg_sizes(const ewdg_ctx* c, int* Np, int* Nfp, int* Nq) {
+  if (!c) return EWDG_EINVAL;
+  if (Np) *Np = c->re.Np;
+  if (Nfp) *Nfp = c->re.Nfp;
+  if (Nq) *Nq = c->re.Nq;
+  return EWDG_OK;
+}
+
+static void map_points(const ewdg_ctx* c, const double* ref, int n, double* xyz) {
+  const MeshData& m = c->mesh;
+  for (int64_t k = 0; k < m.K; ++k)
+    for (int p = 0; p < n; ++p)
+      for (int d = 0; d < 3; ++d) {
+        double x = m.X0[k * 3 + d];
+        for (int cc = 0; cc < 3; ++cc) x += m.A[k * 9 + d * 3 + cc] * (ref[p * 3 + cc] + 1.0);
+        xyz[(k * n + p) * 3 + d] = x;
+      }
+}
+
+int ewdg_node_points(const ewdg_ctx* c, double* xyz) {
+  if (int rc = need(c, true, false, false)) return rc;
+  if (!xyz) return EWDG_EINVAL;
+  std::vector<double> ref(c->re.Np * 3);
+  for (int i = 0; i < c->re.Np; ++i) {
+    ref[i * 3] = c->re.r[i];
+    ref[i * 3 + 1] = c->re.s[i];
+    ref[i * 3 + 2] = c->re.t[i];
+  }
+  map_points(c, ref.data(), c->re.Np, xyz);
+  return EWDG_OK;
+}
+
+int ewdg_quadrature_points(const ewdg_ctx* c, double* xyz) {
+  if (int rc = need(c, true, false, false)) return rc;
+  if (!xyz) return EWDG_EINVAL;
+  map_points(c, c->re.xq.data(), c->re.Nq, xyz);
+  return EWDG_OK;
+}
+
+int ewdg_reference_operator(const ewdg_ctx* c, int which, double* out) {
+  if (!c || !out) return EWDG_EINVAL;
+  const RefElem& re = c->re;
+  const std::vector<double>* src = nullptr;
+  switch (which) {
+    case 0: src = &re.Dr; break;
+    case 1: src = &re.Ds; break;
+    case 2: src = &re.Dt; break;
+    case 3: src = &re.LIFT; break;
+    case 4: src = &re.Vq; break;
+    case 5: src = &re.Pq; break;
+    case 6: src = &re.Mhat; break;
+    case 7:
+      for (int i = 0; i < re.Np; ++i) {
+        out[i * 3] = re.r[i];
+        out[i * 3 + 1] = re.s[i];
+        out[i * 3 + 2] = re.t[i];
+      }
+      return EWDG_OK;
+    case 8: src = &re.wq; break;
+    default: return EWDG_EINVAL;
+  }
+  std::memcpy(out, src->data(), src->size() * sizeof(double));
+  return EWDG_OK;
+}
+
+int ewdg_workspace_bytes(const ewdg_ctx* c, int max_receivers, int max_record_steps, size_t* bytes) {
+  if (int rc = need(c, true, false, false)) return rc;
+  if (!bytes || max_receivers < 0 || max_record_steps < 0) return EWDG_EINVAL;
+  ewdg_ctx tmp;
+  tmp.N = c->N;
+  tmp.prec = c->prec;
+  tmp.re.Np = c->re.Np;
+  tmp.re.Nfp = c->re.Nfp;
+  tmp.re.Nq = c->re.Nq;
+  tmp.mesh.K = c->mesh.K;
+  tmp.max_rec = max_receivers;
+  tmp.max_steps = max_record_steps;
+  *bytes = layout(&tmp, nullptr);
+  return EWDG_OK;
+}
+
+int ewdg_bind_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_receivers, int max_record_steps) {
+  if (int rc = need(c, true, false, false)) return rc;
+  if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
+    return c->fail(EWDG_EINVAL, "workspace must be a non-null 256-byte aligned device pointer");
+  if (max_receivers < 0 || max_record_steps < 0) return c->fail(EWDG_EINVAL, "negative receiver capacity");
+  c->max_rec = max_receivers;
+  c->max_steps = max_record_steps;
+  const size_t need_bytes = layout(c, nullptr);
+  if (bytes < need_bytes) return c->fail(EWDG_ENOMEM, "workspace smaller than ewdg_workspace_bytes");
+  c->ws = static_cast<char*>(ptr);
+  c->ws_bytes = bytes;
+  layout(c, c->ws);
+  const RefElem& re = c->re;
+  const MeshData& m = c->mesh;
+  const int Np = re.Np, Nfp = re.Nfp, Nq = re.Nq;
+  int rc;
+  if ((rc = upload_run(c, c->d.DrT, transpose(re.Dr, Np, Np)))) return rc;
+  if ((rc = upload_run(c, c->d.DsT, transpose(re.Ds, Np, Np)))) return rc;
+  if ((rc = upload_run(c, c->d.DtT, transpose(re.Dt, Np, Np)))) return rc;
+  if ((rc = upload_run(c, c->d.LIFTT, transpose(re.LIFT, Np, 4 * Nfp)))) return rc;
+  if ((rc = upload_run(c, c->d.VqT, transpose(re.Vq, Nq, Np)))) return rc;
+  if ((rc = upload_run(c, c->d.PqT, transpose(re.Pq, Np, Nq)))) return rc;
+  const std::vector<double> Vq64T = transpose(re.Vq, Nq, Np), Pq64T = transpose(re.Pq, Np, Nq);
+  if ((rc = upload(c, c->d.Vq64T, Vq64T.data(), Vq64T.size() * 8))) return rc;
+  if ((rc = upload(c, c->d.Pq64T, Pq64T.data(), Pq64T.size() * 8))) return rc;
+  if ((rc = upload(c, c->d.Mhat64, re.Mhat.data(), re.Mhat.size() * 8))) return rc;
+  if ((rc = upload(c, c->d.wq64, re.wq.data(), re.wq.size() * 8))) return rc;
+  if ((rc = upload_run(c, c->d.geo, m.geo))) return rc;
+  if ((rc = upload_run(c, c->d.fgeo, m.fgeo))) return rc;
+  if ((rc = upload(c, c->d.J64, m.J.data(), m.J.size() * 8))) return rc;
+  if ((rc = upload(c, c->d.conn, m.conn.data(), m.conn.size() * 4))) return rc;
+  std::vector<int32_t> nbn(re.nbrnode.begin(), re.nbrnode.end()), fm(re.Fmask.begin(), re.Fmask.end());
+  if ((rc = upload(c, c->d.nbrnode, nbn.data(), nbn.size() * 4))) return rc;
+  if ((rc = upload(c, c->d.fmask, fm.data(), fm.size() * 4))) return rc;
+  c->bound = true;
+  c->has_material = false;
+  c->has_source = false;
+  c->nr = 0;
+  c->rec_count = 0;
+  return EWDG_OK;
+}
+
+int ewdg_set_material(ewdg_ctx* c, const double* rho, const double* lam, const double* mu) {
+  if (int rc = need(c, true, true, false)) return c ? c->fail(rc, "set_material needs a bound workspace") : rc;
+  if (!rho || !lam || !mu) return EWDG_EINVAL;
+  const int64_t K = c->mesh.K;
+  const int Nq = c->re.Nq;
+  c->cpmax.assign(K, 0.0);
+  for (int64_t k = 0; k < K; ++k)
+    for (int q = 0; q < Nq; ++q) {
+      const double r = rho[k * Nq + q], l = lam[k * Nq + q], u = mu[k * Nq + q];
+      if (!(r > 0.0) || !(u > 0.0) || !(l >= 0.0) || !std::isfinite(r + l + u))
+        return c->fail(EWDG_EINVAL, "material must satisfy rho > 0, mu > 0, lambda >= 0");
+      const double cp = std::sqrt((l + 2.0 * u) / r);
+      if (cp > c->cpmax[k]) c->cpmax[k] = cp;
+    }
+  int rc;
+  const size_t bytes = static_cast<size_t>(K) * Nq * 8;
+  if ((rc = upload(c, c->d.rho64, rho, bytes))) return rc;
+  if ((rc = upload(c, c->d.lam64, lam, bytes))) return rc;
+  if ((rc = upload(c, c->d.mu64, mu, bytes))) return rc;
+  if ((rc = c->hip(launch_material(c->d, c->stream), "material setup"))) return rc;
+  // zero state at t = 0
+  const size_t sb = static_cast<size_t>(K) * c->re.Np * c->tsz();
+  if ((rc = c->hip(hipMemsetAsync(c->d.q[0], 0, 9 * sb, c->stream), "memset"))) return rc;
+  if ((rc = c->hip(hipMemsetAsync(c->d.s[0], 0, 6 * sb, c->stream), "memset"))) return rc;
+  if ((rc = c->hip(hipMemsetAsync(c->d.res, 0, 9 * sb, c->stream), "memset"))) return rc;
+  c->cur = 0;
+  c->t = 0.0;
+  c->has_material = true;
+  if (c->has_source) {
+    if ((rc = c->hip(launch_source_vector(c->d, c->src_elem, c->stream), "source vector"))) return rc;
+  }
+  return c->hip(hipStreamSynchronize(c->stream), "material sync");
+}
+
+int ewdg_set_state(ewdg_ctx* c, const void* q, int on_device, double t) {
+  if (int rc = need(c, true, true, true)) return c ? c->fail(rc, "set_state needs material") : rc;
+  if (!q) return EWDG_EINVAL;
+  const size_t bytes = static_cast<size_t>(c->mesh.K) * 9 * c->re.Np * c->tsz();
+  int rc;
+  c->cur = 0;
+  if ((rc = c->hip(hipMemcpyAsync(c->d.q[0], q, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  c->stream), "set_state copy")))
+    return rc;
+  if ((rc = c->hip(hipMemsetAsync(c->d.res, 0, bytes, c->stream), "memset"))) return rc;
+  if ((rc = c->hip(launch_sigma(c->d, c->d.q[0], c->d.s[0], c->stream), "sigma"))) return rc;
+  c->t = t;
+  if (!on_device) return c->hip(hipStreamSynchronize(c->stream), "set_state sync");
+  return EWDG_OK;
+}
+
+int ewdg_get_state(ewdg_ctx* c, void* q, int on_device, double* t) {
+  if (int rc = need(c, true, true, true)) return rc;
+  if (!q) return EWDG_EINVAL;
+  const size_t bytes = static_cast<size_t>(c->mesh.K) * 9 * c->re.Np * c->tsz();
+  int rc;
+  if ((rc = c->hip(hipMemcpyAsync(q, c->d.q[c->cur], bytes,
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+                   "get_state copy")))
+    return rc;
+  if (t) *t = c->t;
+  if (!on_device) return c->hip(hipStreamSynchronize(c->stream), "get_state sync");
+  return EWDG_OK;
+}
+
+int ewdg_project_quadrature(ewdg_ctx* c, const double* fq, void* q) {
+  if (int rc = need(c, true, true, false)) return rc;
+  if (!fq || !q) return EWDG_EINVAL;
+  return c->hip(launch_project(c->d, fq, q, c->stream), "project");
+}
+
+int ewdg_eval_quadrature(ewdg_ctx* c, const void* q, double* fq) {
+  if (int rc = need(c, true, true, false)) return rc;
+  if (!fq) return EWDG_EINVAL;
+  if (!q) {
+    if (!c->has_material) return EWDG_ESTATE;
+    q = c->d.q[c->cur];
+  }
+  return c->hip(launch_evalq(c->d, q, fq, c->stream), "evalq");
+}
+
+int ewdg_set_source(ewdg_ctx* c, const double xs[3], const double dir[3], double amp, double f0, double t0) {
+  if (int rc = need(c, true, true, false)) return rc;
+  if (!xs || !dir) return EWDG_EINVAL;
+  double rh[3];
+  const int64_t e = locate_point(c->mesh, xs, rh);
+  if (e < 0) return c->fail(EWDG_EPOINT, "source outside the mesh");
+  const std::vector<double> row = nodal_row(c->re, rh);
+  int rc;
+  if ((rc = upload(c, c->d.srcb, row.data(), row.size() * 8))) return rc;
+  c->has_source = true;
+  c->src_elem = e;
+  for (int i = 0; i < 3; ++i) c->src_dir[i] = dir[i];
+  c->src_amp = amp;
+  c->src_f0 = f0;
+  c->src_t0 = t0;
+  if (c->has_material) {
+    if ((rc = c->hip(launch_source_vector(c->d, e, c->stream), "source vector"))) return rc;
+    return c->hip(hipStreamSynchronize(c->stream), "source sync");
+  }
+  return EWDG_OK;
+}
+
+int ewdg_clear_source(ewdg_ctx* c) {
+  if (!c) return EWDG_EINVAL;
+  c->has_source = false;
+  c->src_elem = -1;
+  return EWDG_OK;
+}
+
+int ewdg_set_receivers(ewdg_ctx* c, int nr, const double* xr) {
+  if (int rc = need(c, true, true, false)) return rc;
+  if (nr < 0 || (nr > 0 && !xr)) return EWDG_EINVAL;
+  if (nr > c->max_rec) return c->fail(EWDG_ENOMEM, "more receivers than the workspace capacity");
+  std::vector<double> rows(static_cast<size_t>(nr) * c->re.Np);
+  std::vector<int32_t> el(nr);
+  for (int r = 0; r < nr; ++r) {
+    double rh[3];
+    const int64_t e = locate_point(c->mesh, xr + 3 * r, rh);
+    if (e < 0) return c->fail(EWDG_EPOINT, "receiver outside the mesh");
+    el[r] = static_cast<int32_t>(e);
+    const std::vector<double> row = nodal_row(c->re, rh);
+    std::memcpy(&rows[static_cast<size_t>(r) * c->re.Np], row.data(), row.size() * 8);
+  }
+  int rc;
+  if (nr > 0) {
+    if ((rc = upload(c, c->d.rec_rows, rows.data(), rows.size() * 8))) return rc;
+    if ((rc = upload(c, c->d.rec_elem, el.data(), el.size() * 4))) return rc;
+  }
+  c->nr = nr;
+  c->rec_count = 0;
+  return EWDG_OK;
+}
+
+int ewdg_receivers(ewdg_ctx* c, double* out, int* nsteps) {
+  if (int rc = need(c, true, true, false)) return rc;
+  if (nsteps) *nsteps = c->rec_count;
+  if (!out || c->rec_count == 0 || c->nr == 0) return EWDG_OK;
+  const size_t bytes = static_cast<size_t>(c->rec_count) * c->nr * 3 * 8;
+  int rc;
+  if ((rc = c->hip(hipMemcpyAsync(out, c->d.rec_out, bytes, hipMemcpyDeviceToHost, c->stream), "receivers copy")))
+    return rc;
+  return c->hip(hipStreamSynchronize(c->stream), "receivers sync");
+}
+
+int ewdg_cfl_dt(const ewdg_ctx* c, double cfl, double* dt) {
+  if (!c || !dt || !(cfl > 0.0)) return EWDG_EINVAL;
+  if (!c->has_mesh || c->cpmax.size() != static_cast<size_t>(c->mesh.K)) return EWDG_ESTATE;
+  double mn = 1e300;
+  for (int64_t k = 0; k < c->mesh.K; ++k) mn = std::fmin(mn, c->mesh.inradius[k] / c->cpmax[k]);
+  *dt = cfl * mn / ((c->N + 1.0) * (c->N + 1.0));
+  return EWDG_OK;
+}
+
+static StageCoef coef(const ewdg_ctx* c, double a, double b, double dt, double ts) {
+  StageCoef sc;
+  sc.a = a;
+  sc.b = b;
+  sc.dt = dt;
+  if (c->has_source) {
+    sc.src_elem = c->src_elem;
+    sc.srcval = c->src_amp * ricker(ts, c->src_f0, c->src_t0);
+    for (int i = 0; i < 3; ++i) sc.dir[i] = c->src_dir[i];
+  }
+  return sc;
+}
+
+int ewdg_rhs(ewdg_ctx* c, double t, const void* q, void* rhs) {
+  if (int rc = need(c, true, true, true)) return c ? c->fail(rc, "rhs needs material") : rc;
+  if (!q || !rhs) return EWDG_EINVAL;
+  void* stmp = c->d.s[1 - c->cur];
+  int rc;
+  if ((rc = c->hip(launch_sigma(c->d, q, stmp, c->stream), "sigma"))) return rc;
+  const StageCoef sc = coef(c, 0.0, 0.0, 0.0, t);
+  return c->hip(launch_stage(c->d, 0, q, stmp, nullptr, nullptr, rhs, sc, c->stream), "rhs");
+}
+
+int ewdg_step(ewdg_ctx* c, double dt, int nsteps) {
+  if (int rc = need(c, true, true, true)) return c ? c->fail(rc, "step needs material") : rc;
+  if (nsteps < 0 || !(dt > 0.0)) return EWDG_EINVAL;
+  if (c->nr > 0 && c->rec_count + nsteps > c->max_steps)
+    return c->fail(EWDG_ENOMEM, "receiver record capacity exceeded");
+  int rc;
+  for (int n = 0; n < nsteps; ++n) {
+    for (int i = 0; i < 5; ++i) {
+      const int nx = 1 - c->cur;
+      const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, c->t + kRkC[i] * dt);
+      if ((rc = c->hip(launch_stage(c->d, 1, c->d.q[c->cur], c->d.s[c->cur], c->d.q[nx], c->d.s[nx], c->d.res,
+                                    sc, c->stream),
+                       "stage")))
+        return rc;
+      c->cur = nx;
+    }
+    c->t = c->t + dt;
+    if (c->nr > 0) {
+      if ((rc = c->hip(launch_receivers(c->d, c->d.q[c->cur], c->nr, c->rec_count, c->stream), "receivers")))
+        return rc;
+      ++c->rec_count;
+    }
+  }
+  return EWDG_OK;
+}
+
+int ewdg_time(const ewdg_ctx* c, double* t) {
+  if (!c || !t) return EWDG_EINVAL;
+  *t = c->t;
+  return EWDG_OK;
+}
+
+int ewdg_energy(ewdg_ctx* c, double* E) {
+  if (int rc = need(c, true, true, true)) return rc;
+  if (!E) return EWDG_EINVAL;
+  int rc;
+  if ((rc = c->hip(launch_energy(c->d, c->d.q[c->cur], c->d.scal, c->stream), "energy"))) return rc;
+  if ((rc = c->hip(hipMemcpyAsync(E, c->d.scal, 8, hipMemcpyDeviceToHost, c->stream), "energy copy"))) return rc;
+  return c->hip(hipStreamSynchronize(c->stream), "energy sync");
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Device-side views shared by the host runtime and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ewdg {
+
+// All pointers live inside the caller's workspace.  "Run precision" arrays
+// are float or double according to prec; the others are FP64 or int32.
+struct Dev {
+  int N = 0, prec = 0, Np = 0, Nfp = 0, Nq = 0;
+  int64_t K = 0;
+  // run precision
+  void* q[2] = {nullptr, nullptr};   // [K][9][Np] ping-pong state
+  void* s[2] = {nullptr, nullptr};   // [K][6][Np] sigma_h of q[i]
+  void* res = nullptr;               // [K][9][Np] LSRK register
+  void* W = nullptr;                 // [K][Np][Np], W[k][j][i] = (M_rho^-1 M)_ij
+  void* lm = nullptr;                // [K][2][Nq] lambda, mu at quadrature points
+  void* geo = nullptr;               // [K][9] dr_i/dx_j
+  void* fgeo = nullptr;              // [K][4][4] n_x, n_y, n_z, Fscale
+  void* Z = nullptr;                 // [K][2] Z_p, Z_s
+  void* svec = nullptr;              // [Np] source vector M_rho^-1 phi(x_s)
+  void* DrT = nullptr;               // [Np][Np] transposed derivative matrices
+  void* DsT = nullptr;
+  void* DtT = nullptr;
+  void* LIFTT = nullptr;             // [4Nfp][Np]
+  void* VqT = nullptr;               // [Np][Nq]
+  void* PqT = nullptr;               // [Nq][Np]
+  // FP64
+  double* Vq64T = nullptr;           // [Np][Nq]
+  double* Pq64T = nullptr;           // [Nq][Np]
+  double* Mhat64 = nullptr;          // [Np][Np]
+  double* wq64 = nullptr;            // [Nq]
+  double* rho64 = nullptr;           // [K][Nq]
+  double* lam64 = nullptr;
+  double* mu64 = nullptr;
+  double* J64 = nullptr;             // [K]
+  double* epart = nullptr;           // [K] energy partials
+  double* scal = nullptr;            // [64] small scalars (energy result, source basis)
+  double* srcb = nullptr;            // [Np] nodal basis values at the source point
+  double* msmall = nullptr;          // [Np][Np] scratch for one element's mass inverse
+  double* rec_rows = nullptr;        // [max_rec][Np]
+  int32_t* rec_elem = nullptr;       // [max_rec]
+  double* rec_out = nullptr;         // [max_steps][max_rec][3]
+  // int32
+  int32_t* conn = nullptr;           // [K][4] nbr*32 + g*6 + p
+  int32_t* nbrnode = nullptr;        // [4][4][6][Nfp]
+  int32_t* fmask = nullptr;          // [4][Nfp]
+  // scratch for setup (aliases q[1], s[1], res while no state exists)
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+struct StageCoef {
+  double a = 0, b = 0, dt = 0;       // LSRK coefficients and step
+  double srcval = 0;                 // amp * R(t_stage)
+  double dir[3] = {0, 0, 0};
+  int64_t src_elem = -1;
+};
+
+// Launchers (kernels.hip).  Each returns the launch status.
+hipError_t launch_material(const Dev& d, hipStream_t st);
+hipError_t launch_source_vector(const Dev& d, int64_t elem, hipStream_t st);
+hipError_t launch_sigma(const Dev& d, const void* q, void* s, hipStream_t st);
+// mode 0: rhs = L(qin) written to out; mode 1: LSRK stage, qin/sin -> qout/sout
+hipError_t launch_stage(const Dev& d, int mode, const void* qin, const void* sin, void* qout,
+                        void* sout, void* out, const StageCoef& c, hipStream_t st);
+hipError_t launch_project(const Dev& d, const double* fq, void* q, hipStream_t st);
+hipError_t launch_evalq(const Dev& d, const void* q, double* fq, hipStream_t st);
+hipError_t launch_receivers(const Dev& d, const void* q, int nr, int step, hipStream_t st);
+hipError_t launch_energy(const Dev& d, const void* q, double* out, hipStream_t st);
+bool supported_degree(int N);
+
+}  // namespace ewdg

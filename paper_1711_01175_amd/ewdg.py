@@ -1,0 +1,293 @@
+"""ctypes binding of libewdg.so (declared in include/ewdg.h).
+
+Argument marshalling only: every step of the method runs inside the HIP
+library.  PyTorch supplies device memory (the workspace and the device
+arrays passed in and out) and the HIP stream.  Importing works without a
+GPU; any call that needs the device fails loudly if the library or the GPU
+is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libewdg.so")
+
+EWDG_OK, EWDG_EINVAL, EWDG_ESTATE, EWDG_ENOMEM, EWDG_EHIP, EWDG_EMESH, EWDG_EPOINT = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "EWDG_OK", -1: "EWDG_EINVAL", -2: "EWDG_ESTATE", -3: "EWDG_ENOMEM",
+          -4: "EWDG_EHIP", -5: "EWDG_EMESH", -6: "EWDG_EPOINT"}
+
+_c_p = ctypes.c_void_p
+_c_i = ctypes.c_int
+_c_d = ctypes.c_double
+_c_i64 = ctypes.c_int64
+_c_sz = ctypes.c_size_t
+_P_d = ctypes.POINTER(ctypes.c_double)
+_P_i = ctypes.POINTER(ctypes.c_int)
+
+# name -> argtypes (all return int unless listed in _RESTYPE)
+SIGNATURES = {
+    "ewdg_create": [_c_i, _c_i, _c_p, ctypes.POINTER(_c_p)],
+    "ewdg_destroy": [_c_p],
+    "ewdg_set_stream": [_c_p, _c_p],
+    "ewdg_set_mesh": [_c_p, _c_i64, _c_p, _c_p],
+    "ewdg_sizes": [_c_p, _P_i, _P_i, _P_i],
+    "ewdg_node_points": [_c_p, _c_p],
+    "ewdg_quadrature_points": [_c_p, _c_p],
+    "ewdg_reference_operator": [_c_p, _c_i, _c_p],
+    "ewdg_workspace_bytes": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
+    "ewdg_bind_workspace": [_c_p, _c_p, _c_sz, _c_i, _c_i],
+    "ewdg_set_material": [_c_p, _c_p, _c_p, _c_p],
+    "ewdg_set_state": [_c_p, _c_p, _c_i, _c_d],
+    "ewdg_get_state": [_c_p, _c_p, _c_i, _P_d],
+    "ewdg_project_quadrature": [_c_p, _c_p, _c_p],
+    "ewdg_eval_quadrature": [_c_p, _c_p, _c_p],
+    "ewdg_set_source": [_c_p, _c_p, _c_p, _c_d, _c_d, _c_d],
+    "ewdg_clear_source": [_c_p],
+    "ewdg_set_receivers": [_c_p, _c_i, _c_p],
+    "ewdg_receivers": [_c_p, _c_p, _P_i],
+    "ewdg_cfl_dt": [_c_p, _c_d, _P_d],
+    "ewdg_rhs": [_c_p, _c_d, _c_p, _c_p],
+    "ewdg_step": [_c_p, _c_d, _c_i],
+    "ewdg_time": [_c_p, _P_d],
+    "ewdg_energy": [_c_p, _P_d],
+    "ewdg_last_error": [_c_p],
+}
+_RESTYPE = {"ewdg_last_error": ctypes.c_char_p}
+
+_lib = None
+
+
+def load():
+    """Load libewdg.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libewdg.so is not built (run __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = _RESTYPE.get(name, ctypes.c_int)
+        _lib = lib
+    return _lib
+
+
+class EwdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    """Raw pointer of a numpy array or torch tensor (must be contiguous)."""
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous
+        return ctypes.c_void_p(a.ctypes.data)
+    assert a.is_contiguous()
+    return ctypes.c_void_p(a.data_ptr())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """One ewdg context: a mesh, a degree, a precision and a workspace.
+
+    Methods mirror the C entry points (ewdg_<name>)."""
+
+    def __init__(self, N, precision=64, stream=None):
+        self.lib = load()
+        self.N = int(N)
+        self.precision = int(precision)
+        self._ws = None
+        h = _c_p()
+        rc = self.lib.ewdg_create(self.N, self.precision, _c_p(stream), ctypes.byref(h))
+        if rc != EWDG_OK:
+            raise EwdgError(rc, f"ewdg_create(N={N}, precision={precision}) failed")
+        self.h = h
+        Np, Nfp, Nq = _c_i(), _c_i(), _c_i()
+        self._check(self.lib.ewdg_sizes(self.h, ctypes.byref(Np), ctypes.byref(Nfp), ctypes.byref(Nq)))
+        self.Np, self.Nfp, self.Nq = Np.value, Nfp.value, Nq.value
+        self.K = 0
+
+    # -------------------------------------------------------------- plumbing
+    def _check(self, rc, what=""):
+        if rc != EWDG_OK:
+            msg = self.lib.ewdg_last_error(self.h) if getattr(self, "h", None) else b""
+            raise EwdgError(rc, f"{what} {msg.decode() if msg else ''}".strip())
+
+    def _shape(self, t, per_elem):
+        if t.numel() != self.K * per_elem:
+            raise EwdgError(EWDG_EINVAL, f"array has {t.numel()} values, expected {self.K * per_elem}")
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float32 if self.precision == 32 else torch.float64
+
+    @property
+    def np_dtype(self):
+        return np.float32 if self.precision == 32 else np.float64
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ewdg_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._check(self.lib.ewdg_set_stream(self.h, _c_p(stream)), "set_stream")
+
+    # ----------------------------------------------------------------- mesh
+    def set_mesh(self, EToV, VXYZ):
+        EToV = _host(EToV, np.int64)
+        VXYZ = _host(VXYZ, np.float64)
+        K = EToV.shape[0]
+        assert EToV.shape == (K, 4) and VXYZ.shape == (K, 4, 3)
+        self._check(self.lib.ewdg_set_mesh(self.h, K, _ptr(EToV), _ptr(VXYZ)), "set_mesh")
+        self.K = K
+
+    def node_points(self):
+        out = np.empty((self.K, self.Np, 3))
+        self._check(self.lib.ewdg_node_points(self.h, _ptr(out)), "node_points")
+        return out
+
+    def quadrature_points(self):
+        out = np.empty((self.K, self.Nq, 3))
+        self._check(self.lib.ewdg_quadrature_points(self.h, _ptr(out)), "quadrature_points")
+        return out
+
+    def reference_operator(self, which):
+        Np, Nfp, Nq = self.Np, self.Nfp, self.Nq
+        shapes = {0: (Np, Np), 1: (Np, Np), 2: (Np, Np), 3: (Np, 4 * Nfp), 4: (Nq, Np),
+                  5: (Np, Nq), 6: (Np, Np), 7: (Np, 3), 8: (Nq,)}
+        out = np.empty(shapes[which])
+        self._check(self.lib.ewdg_reference_operator(self.h, which, _ptr(out)), "reference_operator")
+        return out
+
+    # ------------------------------------------------------------ workspace
+    def workspace_bytes(self, max_receivers=0, max_record_steps=0):
+        b = _c_sz()
+        self._check(self.lib.ewdg_workspace_bytes(self.h, max_receivers, max_record_steps,
+                                                  ctypes.byref(b)), "workspace_bytes")
+        return b.value
+
+    def bind_workspace(self, max_receivers=0, max_record_steps=0, buffer=None):
+        """Bind a torch-allocated device buffer (allocated here if not given)."""
+        torch = _torch()
+        nbytes = self.workspace_bytes(max_receivers, max_record_steps)
+        if buffer is None:
+            buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._check(self.lib.ewdg_bind_workspace(self.h, _ptr(buffer), buffer.numel() * buffer.element_size(),
+                                                 max_receivers, max_record_steps), "bind_workspace")
+        self._ws = buffer
+        return buffer
+
+    # ------------------------------------------------------------- material
+    def set_material(self, rho_q, lam_q, mu_q):
+        shp = (self.K, self.Nq)
+        r, l, m = (_host(x, np.float64).reshape(shp) for x in (rho_q, lam_q, mu_q))
+        self._check(self.lib.ewdg_set_material(self.h, _ptr(r), _ptr(l), _ptr(m)), "set_material")
+
+    # ---------------------------------------------------------------- state
+    def set_state(self, q, t=0.0):
+        torch = _torch()
+        if isinstance(q, np.ndarray):
+            qh = _host(q, self.np_dtype)
+            if qh.size != self.K * 9 * self.Np:
+                raise EwdgError(EWDG_EINVAL, "state has the wrong size")
+            self._check(self.lib.ewdg_set_state(self.h, _ptr(qh), 0, float(t)), "set_state")
+        else:
+            qd = q.to(device="cuda", dtype=self.torch_dtype).contiguous()
+            self._shape(qd, 9 * self.Np)
+            self._check(self.lib.ewdg_set_state(self.h, _ptr(qd), 1, float(t)), "set_state")
+            torch.cuda.current_stream().synchronize()
+
+    def get_state(self):
+        torch = _torch()
+        out = torch.empty((self.K, 9, self.Np), dtype=self.torch_dtype, device="cuda")
+        t = _c_d()
+        self._check(self.lib.ewdg_get_state(self.h, _ptr(out), 1, ctypes.byref(t)), "get_state")
+        return out
+
+    def project_quadrature(self, fq):
+        torch = _torch()
+        fq = fq.to(device="cuda", dtype=torch.float64).contiguous()
+        self._shape(fq, 9 * self.Nq)
+        out = torch.empty((self.K, 9, self.Np), dtype=self.torch_dtype, device="cuda")
+        self._check(self.lib.ewdg_project_quadrature(self.h, _ptr(fq), _ptr(out)), "project_quadrature")
+        return out
+
+    def eval_quadrature(self, q=None):
+        torch = _torch()
+        out = torch.empty((self.K, 9, self.Nq), dtype=torch.float64, device="cuda")
+        if q is not None:
+            assert q.is_cuda and q.dtype == self.torch_dtype and q.is_contiguous()
+            self._shape(q, 9 * self.Np)
+        qp = _c_p(None) if q is None else _ptr(q)
+        self._check(self.lib.ewdg_eval_quadrature(self.h, qp, _ptr(out)), "eval_quadrature")
+        return out
+
+    # ------------------------------------------------- source and receivers
+    def set_source(self, xs, direction, amp, f0, t0):
+        xs = _host(xs, np.float64)
+        d = _host(direction, np.float64)
+        self._check(self.lib.ewdg_set_source(self.h, _ptr(xs), _ptr(d), float(amp), float(f0), float(t0)),
+                    "set_source")
+
+    def clear_source(self):
+        self._check(self.lib.ewdg_clear_source(self.h), "clear_source")
+
+    def set_receivers(self, xr):
+        xr = _host(xr, np.float64).reshape(-1, 3)
+        self._check(self.lib.ewdg_set_receivers(self.h, xr.shape[0], _ptr(xr)), "set_receivers")
+        self.nr = xr.shape[0]
+
+    def receivers(self):
+        n = _c_i()
+        self._check(self.lib.ewdg_receivers(self.h, _c_p(None), ctypes.byref(n)), "receivers")
+        out = np.zeros((n.value, self.nr, 3))
+        if n.value and self.nr:
+            self._check(self.lib.ewdg_receivers(self.h, _ptr(out), ctypes.byref(n)), "receivers")
+        return out
+
+    # ------------------------------------------------------------- stepping
+    def cfl_dt(self, cfl):
+        dt = _c_d()
+        self._check(self.lib.ewdg_cfl_dt(self.h, float(cfl), ctypes.byref(dt)), "cfl_dt")
+        return dt.value
+
+    def rhs(self, t, q):
+        torch = _torch()
+        q = q.to(device="cuda", dtype=self.torch_dtype).contiguous()
+        self._shape(q, 9 * self.Np)
+        out = torch.empty_like(q)
+        self._check(self.lib.ewdg_rhs(self.h, float(t), _ptr(q), _ptr(out)), "rhs")
+        return out
+
+    def step(self, dt, nsteps):
+        self._check(self.lib.ewdg_step(self.h, float(dt), int(nsteps)), "step")
+
+    def time(self):
+        t = _c_d()
+        self._check(self.lib.ewdg_time(self.h, ctypes.byref(t)), "time")
+        return t.value
+
+    def energy(self):
+        e = _c_d()
+        self._check(self.lib.ewdg_energy(self.h, ctypes.byref(e)), "energy")
+        return e.value
