@@ -87,8 +87,16 @@ int ewdg_quadrature_points(const ewdg_ctx* ctx, double* xyz);
 /* Reference-element operators (host, FP64, row-major) for inspection:
  * which = 0 Dr, 1 Ds, 2 Dt [Np][Np]; 3 LIFT [Np][4Nfp]; 4 Vq [Nq][Np];
  * 5 Pq [Np][Nq]; 6 reference mass [Np][Np]; 7 nodes (r,s,t) [Np][3];
- * 8 quadrature weights [Nq]. */
+ * 8 quadrature weights [Nq]; 9 face node list [4][Nfp] (volume node
+ * indices); 10 neighbour node table [4][4][6][Nfp]: volume node, in the
+ * neighbour, of face node j of face f when the neighbour's face is g and
+ * the vertex correspondence is permutation p. */
 int ewdg_reference_operator(const ewdg_ctx* ctx, int which, double* out);
+/* Face connectivity, host int32 [K][4]: nbr*32 + g*6 + p (neighbour
+ * element, its matching face g, vertex permutation p with our face vertex m
+ * at the neighbour's face position perm_p(m), perm_0..5 = 012, 021, 102,
+ * 120, 201, 210).  Requires the mesh. */
+int ewdg_connectivity(const ewdg_ctx* ctx, int32_t* conn);
 
 /* Device workspace needed for the mesh plus up to max_receivers receivers
  * recorded over up to max_record_steps steps.  Requires the mesh. */

@@ -280,9 +280,22 @@ int ewdg_reference_operator(const ewdg_ctx* c, int which, double* out) {
       }
       return EWDG_OK;
     case 8: src = &re.wq; break;
+    case 9:
+      for (size_t i = 0; i < re.Fmask.size(); ++i) out[i] = re.Fmask[i];
+      return EWDG_OK;
+    case 10:
+      for (size_t i = 0; i < re.nbrnode.size(); ++i) out[i] = re.nbrnode[i];
+      return EWDG_OK;
     default: return EWDG_EINVAL;
   }
   std::memcpy(out, src->data(), src->size() * sizeof(double));
+  return EWDG_OK;
+}
+
+int ewdg_connectivity(const ewdg_ctx* c, int32_t* conn) {
+  if (int rc = need(c, true, false, false)) return rc;
+  if (!conn) return EWDG_EINVAL;
+  std::memcpy(conn, c->mesh.conn.data(), c->mesh.conn.size() * 4);
   return EWDG_OK;
 }
 

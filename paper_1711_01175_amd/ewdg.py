@@ -36,6 +36,7 @@ SIGNATURES = {
     "ewdg_node_points": [_c_p, _c_p],
     "ewdg_quadrature_points": [_c_p, _c_p],
     "ewdg_reference_operator": [_c_p, _c_i, _c_p],
+    "ewdg_connectivity": [_c_p, _c_p],
     "ewdg_workspace_bytes": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
     "ewdg_bind_workspace": [_c_p, _c_p, _c_sz, _c_i, _c_i],
     "ewdg_set_material": [_c_p, _c_p, _c_p, _c_p],
@@ -174,9 +175,14 @@ class Context:
     def reference_operator(self, which):
         Np, Nfp, Nq = self.Np, self.Nfp, self.Nq
         shapes = {0: (Np, Np), 1: (Np, Np), 2: (Np, Np), 3: (Np, 4 * Nfp), 4: (Nq, Np),
-                  5: (Np, Nq), 6: (Np, Np), 7: (Np, 3), 8: (Nq,)}
+                  5: (Np, Nq), 6: (Np, Np), 7: (Np, 3), 8: (Nq,), 9: (4, Nfp), 10: (4, 4, 6, Nfp)}
         out = np.empty(shapes[which])
         self._check(self.lib.ewdg_reference_operator(self.h, which, _ptr(out)), "reference_operator")
+        return out
+
+    def connectivity(self):
+        out = np.empty((self.K, 4), dtype=np.int32)
+        self._check(self.lib.ewdg_connectivity(self.h, _ptr(out)), "connectivity")
         return out
 
     # ------------------------------------------------------------ workspace
