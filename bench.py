@@ -73,6 +73,25 @@ def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ):
     return out
 
 
+def probe_copy(nbytes=2 << 30, reps=5):
+    """Plain device-to-device copy of nbytes (read nbytes + write nbytes):
+    the reference for scaling HBM counters and for achievable bandwidth."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    ev1.record()
+    torch.cuda.synchronize()
+    s = ev0.elapsed_time(ev1) * 1e-3 / reps
+    print(json.dumps({"probe": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "seconds": s, "GBs_read_plus_write": 2 * nbytes / s / 1e9}), flush=True)
+
+
 def cpu_baseline(N, n_sample, seconds):
     """Time the FP64 oracle's RHS on a smaller mesh of the same workload
     (per-element work does not depend on the mesh size)."""
@@ -115,6 +134,8 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-n", type=int, default=8)
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="time a plain device copy of 2 GiB instead (HBM calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -122,6 +143,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.probe_copy:
+        probe_copy()
+        return
     EToV, VXYZ, _ = build_workload(args.n, args.N)
     r32 = run_gpu(32, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)
     r64 = None if args.skip_fp64 else run_gpu(64, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)

@@ -65,6 +65,15 @@ struct ewdg_ctx {
 
 namespace {
 
+size_t pad_to(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+// Copy a row-major [rows][cols] block into a zero [R][C] array at (r0, c0).
+void place(std::vector<double>& dst, size_t C, const std::vector<double>& src, int rows, int cols,
+           size_t r0, size_t c0) {
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) dst[(r0 + i) * C + c0 + j] = src[static_cast<size_t>(i) * cols + j];
+}
+
 // Sequential 256-byte aligned layout of the workspace.  With base == nullptr
 // only the total size is computed.
 size_t layout(ewdg_ctx* c, char* base) {
@@ -92,10 +101,13 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.fgeo = take(16 * K * ts);
   d.Z = take(2 * K * ts);
   d.svec = take(Np * ts);
-  d.DrT = take(Np * Np * ts);
-  d.DsT = take(Np * Np * ts);
-  d.DtT = take(Np * Np * ts);
-  d.LIFTT = take(4 * Nfp * Np * ts);
+  const size_t NpR = pad_to(Np, 16), NpK = pad_to(Np, 4), NqR = pad_to(Nq, 16), NqK = pad_to(Nq, 4),
+               NfpK = pad_to(Nfp, 4);
+  // fragment-ordered operators: (row tiles) x (k-steps) x 64 values
+  d.Dpad = take(3 * (NpR / 16) * (NpK / 4) * 64 * ts);
+  d.Lpad = take(4 * (NpR / 16) * (NfpK / 4) * 64 * ts);
+  d.Vqpad = take((NqR / 16) * (NpK / 4) * 64 * ts);
+  d.Pqpad = take((NpR / 16) * (NqK / 4) * 64 * ts);
   d.VqT = take(Nq * Np * ts);
   d.PqT = take(Nq * Np * ts);
   d.Vq64T = reinterpret_cast<double*>(take(Nq * Np * 8));
@@ -331,10 +343,39 @@ int ewdg_bind_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_receivers,
   const MeshData& m = c->mesh;
   const int Np = re.Np, Nfp = re.Nfp, Nq = re.Nq;
   int rc;
-  if ((rc = upload_run(c, c->d.DrT, transpose(re.Dr, Np, Np)))) return rc;
-  if ((rc = upload_run(c, c->d.DsT, transpose(re.Ds, Np, Np)))) return rc;
-  if ((rc = upload_run(c, c->d.DtT, transpose(re.Dt, Np, Np)))) return rc;
-  if ((rc = upload_run(c, c->d.LIFTT, transpose(re.LIFT, Np, 4 * Nfp)))) return rc;
+  {
+    // matrix-core fragment order: block (row tile R, k-step kk) holds 64
+    // values, lane l taking A[16R + l%16][4kk + l/16] (zero outside A)
+    auto frag = [](const std::vector<double>& A, int rows, int cols, int RT, int KS, std::vector<double>& out,
+                   size_t base) {
+      for (int R = 0; R < RT; ++R)
+        for (int kk = 0; kk < KS; ++kk)
+          for (int l = 0; l < 64; ++l) {
+            const int i = 16 * R + l % 16, j = 4 * kk + l / 16;
+            out[base + (static_cast<size_t>(R) * KS + kk) * 64 + l] =
+                (i < rows && j < cols) ? A[static_cast<size_t>(i) * cols + j] : 0.0;
+          }
+    };
+    const int RT = static_cast<int>(pad_to(Np, 16) / 16), QT = static_cast<int>(pad_to(Nq, 16) / 16);
+    const int KD = static_cast<int>(pad_to(Np, 4) / 4), KF = static_cast<int>(pad_to(Nfp, 4) / 4),
+              KQ = static_cast<int>(pad_to(Nq, 4) / 4);
+    std::vector<double> Dp(3 * RT * KD * 64), Lp(4 * RT * KF * 64), Vp(QT * KD * 64), Pp(RT * KQ * 64);
+    frag(re.Dr, Np, Np, RT, KD, Dp, 0);
+    frag(re.Ds, Np, Np, RT, KD, Dp, static_cast<size_t>(RT) * KD * 64);
+    frag(re.Dt, Np, Np, RT, KD, Dp, 2 * static_cast<size_t>(RT) * KD * 64);
+    for (int f = 0; f < 4; ++f) {
+      std::vector<double> Lf(static_cast<size_t>(Np) * Nfp);
+      for (int i = 0; i < Np; ++i)
+        for (int j = 0; j < Nfp; ++j) Lf[i * Nfp + j] = re.LIFT[i * 4 * Nfp + f * Nfp + j];
+      frag(Lf, Np, Nfp, RT, KF, Lp, static_cast<size_t>(f) * RT * KF * 64);
+    }
+    frag(re.Vq, Nq, Np, QT, KD, Vp, 0);
+    frag(re.Pq, Np, Nq, RT, KQ, Pp, 0);
+    if ((rc = upload_run(c, c->d.Dpad, Dp))) return rc;
+    if ((rc = upload_run(c, c->d.Lpad, Lp))) return rc;
+    if ((rc = upload_run(c, c->d.Vqpad, Vp))) return rc;
+    if ((rc = upload_run(c, c->d.Pqpad, Pp))) return rc;
+  }
   if ((rc = upload_run(c, c->d.VqT, transpose(re.Vq, Nq, Np)))) return rc;
   if ((rc = upload_run(c, c->d.PqT, transpose(re.Pq, Np, Nq)))) return rc;
   const std::vector<double> Vq64T = transpose(re.Vq, Nq, Np), Pq64T = transpose(re.Pq, Np, Nq);

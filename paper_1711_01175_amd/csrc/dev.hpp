@@ -22,10 +22,12 @@ struct Dev {
   void* fgeo = nullptr;              // [K][4][4] n_x, n_y, n_z, Fscale
   void* Z = nullptr;                 // [K][2] Z_p, Z_s
   void* svec = nullptr;              // [Np] source vector M_rho^-1 phi(x_s)
-  void* DrT = nullptr;               // [Np][Np] transposed derivative matrices
-  void* DsT = nullptr;
-  void* DtT = nullptr;
-  void* LIFTT = nullptr;             // [4Nfp][Np]
+  // operators in matrix-core fragment order (see the stage kernel):
+  // [row tile][k-step][64 lanes], zero padded
+  void* Dpad = nullptr;              // Dr, Ds, Dt
+  void* Lpad = nullptr;              // LIFT, one block per face
+  void* Vqpad = nullptr;             // nodes -> quadrature points
+  void* Pqpad = nullptr;             // quadrature points -> nodes (L2_Q projection)
   void* VqT = nullptr;               // [Np][Nq]
   void* PqT = nullptr;               // [Nq][Np]
   // FP64

@@ -18,16 +18,56 @@ struct Sz {
   static constexpr int BUF = cmax(9 * Np, cmax(9 * NF, 6 * Nq));
 };
 
-// Elements per workgroup of the stage kernel: as many as fill ~256 node
-// threads while the staged element data stays within 64 KiB of LDS.
-template <typename T, int N>
-struct StageCfg {
+// ---------------------------------------------------------------- MFMA tiles
+// 16x16x4 matrix-core tiles: C[16x16] += A[16x4] B[4x16].  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16].  Register r of the accumulator holds
+// column l%16 and row row(l/16, r): 4(l/16)+r for FP32, 4r+(l/16) for FP64
+// (measured with a layout probe on gfx950).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
+};
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lg, int r) { return 4 * r + lg; }
+};
+
+constexpr int ceil_to(int x, int m) { return (x + m - 1) / m * m; }
+constexpr int cmax2(int a, int b) { return a > b ? a : b; }
+
+// Padded shapes of the stage kernel.  A workgroup owns a tile of 16
+// elements; matrix columns are (field, element) pairs, 16 per field.
+template <int N>
+struct Tile {
   using S = Sz<N>;
-  static constexpr int per_elem = 18 * S::Np + S::BUF + 32;
-  static constexpr int e_lds = (64 * 1024) / (per_elem * static_cast<int>(sizeof(T)));
-  static constexpr int e_thr = 256 / S::Np > 0 ? 256 / S::Np : 1;
-  static constexpr int E = (e_lds < e_thr ? e_lds : e_thr) > 0 ? (e_lds < e_thr ? e_lds : e_thr) : 1;
-  static constexpr int NT = ((E * S::Np + 63) / 64) * 64;
+  static constexpr int Np = S::Np, Nfp = S::Nfp, Nq = S::Nq;
+  static constexpr int E = 16;
+  static constexpr int NpK = ceil_to(Np, 4);    // node index as the K dimension
+  static constexpr int NpR = ceil_to(Np, 16);   // node index as the row dimension
+  static constexpr int NqK = ceil_to(Nq, 4);
+  static constexpr int NqR = ceil_to(Nq, 16);
+  static constexpr int NfpK = ceil_to(Nfp, 4);  // face nodes of one face as K
+  static constexpr int RT = NpR / 16;           // node row tiles
+  static constexpr int QT = NqR / 16;           // quadrature row tiles
+  static constexpr int NW = RT > 4 ? 8 : 4;     // waves: at most one node row tile each
+  static constexpr int NT = 64 * NW;
+  // LDS regions (in values): X holds v and the contravariant stresses, later
+  // the velocity right-hand side and then the new strains; Y holds one face's
+  // interface corrections, later the stresses at the quadrature points.
+  static constexpr int X = cmax2(2 * NpK * 48, NpK * 96);
+  static constexpr int QC = NqR < 128 ? NqR : 128;  // quadrature rows per chunk (whole tiles)
+  static constexpr int Y = cmax2(NfpK * 144, QC * 48);
+  static constexpr int GEO = E * 32;
 };
 
 template <typename T>
@@ -43,12 +83,12 @@ struct StageArgs {
   const T* fgeo;
   const T* Z;
   const T* svec;
-  const T* DrT;
-  const T* DsT;
-  const T* DtT;
-  const T* LIFTT;
-  const T* VqT;
-  const T* PqT;
+  // operators pre-arranged in matrix-core fragment order: for row tile R and
+  // k-step kk, 64 consecutive values hold A[16R + l%16][4kk + l/16], l = lane
+  const T* Dpad;     // [3][RT][NpK/4][64]
+  const T* Lpad;     // [4 faces][RT][NfpK/4][64]
+  const T* Vqpad;    // [QT][NpK/4][64]
+  const T* Pqpad;    // [RT][NqK/4][64]
   const int32_t* conn;
   const int32_t* nbrnode;
   const int32_t* fmask;
@@ -85,152 +125,290 @@ __device__ __forceinline__ void interface_state(const T* n, const T* vm, const T
   }
 }
 
+// Maps workgroups to element tiles so that each of the 8 XCDs (which own
+// separate L2 caches and receive workgroups round-robin) works on a
+// contiguous range of the mesh, keeping face neighbours in the same L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
+  if (nblk % 8 != 0) return bid;
+  return (bid % 8) * (nblk / 8) + bid / 8;
+}
+
+// Face-point data gathered for one face ahead of its use: own stresses and
+// the neighbour's velocity and stresses at the matching node.
+template <typename T>
+struct FacePt {
+  T sm[6], vp[3], sp[6], zp, zs;
+};
+
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((StageCfg<T, N>::NT)) void k_stage(StageArgs<T> a) {
-  using S = Sz<N>;
-  using C = StageCfg<T, N>;
-  constexpr int Np = S::Np, Nfp = S::Nfp, Nq = S::Nq, NF = S::NF, BUF = S::BUF;
-  constexpr int E = C::E, NT = C::NT;
-  __shared__ T sq[E * 9 * Np];
-  __shared__ T ss[E * 6 * Np];
-  __shared__ T sb[E * BUF];
-  __shared__ T sr[E * 3 * Np];
-  __shared__ T sg[E * 32];
+__global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage(StageArgs<T> a) {
+  using TL = Tile<N>;
+  using M = Mfma<T>;
+  using acc_t = typename M::acc_t;
+  constexpr int Np = TL::Np, Nfp = TL::Nfp, Nq = TL::Nq, E = TL::E;
+  constexpr int NpK = TL::NpK, NqK = TL::NqK, NfpK = TL::NfpK;
+  constexpr int RT = TL::RT, QT = TL::QT, NW = TL::NW, NT = TL::NT;
+  constexpr int KD = NpK / 4, KF = NfpK / 4;       // k-steps of the node / face contractions
+  constexpr int FPT = (Nfp * E + NT - 1) / NT;      // face points per thread and face
+  __shared__ T sX[TL::X];
+  __shared__ T sY[TL::Y];
+  __shared__ T sgeo[TL::GEO];
   const int tid = threadIdx.x;
-  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * E;
-  const int ne = static_cast<int>((a.K - e0) < E ? (a.K - e0) : E);
+  const int w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lg = l >> 4;  // A row / B column; K sub-index
+  const int Ke = static_cast<int>(a.K);
+  const int nblk = (Ke + E - 1) / E;
+  const int e0 = static_cast<int>(xcd_tile(blockIdx.x, nblk)) * E;
+  const bool own = w < RT;             // this wave owns node row tile R = w
+  const int R = w;
 
-  for (int x = tid; x < ne * 9 * Np; x += NT) sq[x] = a.qin[e0 * 9 * Np + x];
-  for (int x = tid; x < ne * 6 * Np; x += NT) ss[x] = a.sin[e0 * 6 * Np + x];
-  for (int x = tid; x < ne * 27; x += NT) {
-    const int e = x / 27, m = x % 27;
-    T v;
-    if (m < 9) v = a.geo[(e0 + e) * 9 + m];
-    else if (m < 25) v = a.fgeo[(e0 + e) * 16 + (m - 9)];
-    else v = a.Z[(e0 + e) * 2 + (m - 25)];
-    sg[e * 32 + m] = v;
-  }
-  __syncthreads();
-
-  // Contravariant stress components G_c^k = sum_m (dr_k/dx_m) sigma_cm.
-  for (int x = tid; x < ne * Np; x += NT) {
-    const int e = x / Np, j = x % Np;
-    const T* sp = &ss[e * 6 * Np + j];
-    const T sxx = sp[0], syy = sp[Np], szz = sp[2 * Np], syz = sp[3 * Np], sxz = sp[4 * Np],
-            sxy = sp[5 * Np];
-    const T row[3][3] = {{sxx, sxy, sxz}, {sxy, syy, syz}, {sxz, syz, szz}};
-    const T* g = &sg[e * 32];
+  // ---- face-point gathers, one face ahead of use: own stresses and the
+  // neighbour's velocity and stresses at the matching node.
+  auto gather = [&](int f, FacePt<T>* pf) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int p = 0; p < FPT; ++p) {
+      const int x = tid + p * NT;
+      const int e = x / Nfp, j = x % Nfp;   // element-major: lanes share a neighbour's cache lines
+      if (x < Nfp * E && e0 + e < Ke) {
+        const int32_t wd = a.conn[(e0 + e) * 4 + f];
+        const int code = wd & 31;
+        const int nb = wd >> 5;
+        const int nn = a.nbrnode[((f * 4 + code / 6) * 6 + code % 6) * Nfp + j];
+        const int il = a.fmask[f * Nfp + j];
+        const T* so = a.sin + (e0 + e) * 6 * Np + il;
+        const T* qn = a.qin + nb * 9 * Np + nn;
+        const T* sn = a.sin + nb * 6 * Np + nn;
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        sb[e * BUF + (c * 3 + k) * Np + j] =
-            g[k * 3 + 0] * row[c][0] + g[k * 3 + 1] * row[c][1] + g[k * 3 + 2] * row[c][2];
-  }
-  __syncthreads();
-
-  const bool act = tid < ne * Np;
-  const int e = act ? tid / Np : 0, i = act ? tid % Np : 0;
-  T rhs[9];
-  if (act) {
-    T div[3] = {0, 0, 0};
-    T gv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    const T* G = &sb[e * BUF];
-    const T* v = &sq[e * 9 * Np];
-    for (int j = 0; j < Np; ++j) {
-      const T dr = a.DrT[j * Np + i], ds = a.DsT[j * Np + i], dt = a.DtT[j * Np + i];
+        for (int m = 0; m < 6; ++m) pf[p].sm[m] = so[m * Np];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        div[c] += dr * G[(c * 3 + 0) * Np + j] + ds * G[(c * 3 + 1) * Np + j] +
-                  dt * G[(c * 3 + 2) * Np + j];
-        const T vc = v[c * Np + j];
-        gv[c][0] += dr * vc;
-        gv[c][1] += ds * vc;
-        gv[c][2] += dt * vc;
+        for (int c = 0; c < 3; ++c) pf[p].vp[c] = qn[c * Np];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) pf[p].sp[m] = sn[m * Np];
+        pf[p].zp = a.Z[nb * 2];
+        pf[p].zs = a.Z[nb * 2 + 1];
       }
     }
-    const T* g = &sg[e * 32];
-    T gr[3][3];
+  };
+
+  // ---- element data: geometry, velocities (B layout), zero paddings
+  for (int x = tid; x < E * 27; x += NT) {
+    const int e = x / 27, m = x % 27;
+    T v = T(0);
+    if (e0 + e < Ke) {
+      if (m < 9) v = a.geo[(e0 + e) * 9 + m];
+      else if (m < 25) v = a.fgeo[(e0 + e) * 16 + (m - 9)];
+      else v = a.Z[(e0 + e) * 2 + (m - 25)];
+    }
+    sgeo[e * 32 + m] = v;
+  }
+  T* Sv = sX;                // [NpK][48]  v_c of element e at column c*16+e
+  T* SG = sX + NpK * 48;     // [NpK][48]  G^k_c for the current direction k
+  for (int x = tid; x < E * 3 * Np; x += NT) {
+    const int e = x / (3 * Np), rem = x % (3 * Np), c = rem / Np, j = rem % Np;
+    const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+    const T v = a.qin[ge * 9 * Np + c * Np + j];
+    Sv[j * 48 + c * 16 + e] = (e0 + e < Ke) ? v : T(0);
+  }
+  for (int x = tid; x < (NpK - Np) * 48; x += NT) {
+    Sv[Np * 48 + x] = T(0);
+    SG[Np * 48 + x] = T(0);
+  }
+  constexpr int NPT = (E * Np + NT - 1) / NT;
+  FacePt<T> pf[FPT];
+  gather(0, pf);   // in flight during the volume terms
+  __syncthreads();
+
+  // ---- volume terms: div sigma = sum_k D_k G^k with the contravariant
+  // stresses G^k_c = sum_m (dr_k/dx_m) sigma_cm, and sym grad v folded into
+  // the strain rows direction by direction.
+  acc_t rhs[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) rhs[c] = acc_t{0, 0, 0, 0};
+  const T* gl = &sgeo[lr * 32];   // geometry of this lane's element
+#pragma unroll 1
+  for (int k = 0; k < 3; ++k) {
+    T af[KD];
+    if (own) {
+      const T* D = a.Dpad + ((k * RT + R) * KD) * 64 + l;
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) af[kk] = D[kk * 64];
+    }
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+      const int x = tid + p * NT;
+      if (x < E * Np) {
+        const int e = x / Np, j = x % Np;
+        T sg[6];
+        const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) sg[m] = a.sin[ge * 6 * Np + m * Np + j];
+        const T* g = &sgeo[e * 32 + k * 3];
+        // rows of sigma in Voigt order xx,yy,zz,yz,xz,xy
+        SG[j * 48 + 0 * 16 + e] = g[0] * sg[0] + g[1] * sg[5] + g[2] * sg[4];
+        SG[j * 48 + 1 * 16 + e] = g[0] * sg[5] + g[1] * sg[1] + g[2] * sg[3];
+        SG[j * 48 + 2 * 16 + e] = g[0] * sg[4] + g[1] * sg[3] + g[2] * sg[2];
+      }
+    }
+    __syncthreads();
+    if (own) {
+      acc_t gv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gv[c] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) {
+        const int row = (4 * kk + lg) * 48 + lr;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          rhs[c] = M::mma(af[kk], SG[row + c * 16], rhs[c]);
+          gv[c] = M::mma(af[kk], Sv[row + c * 16], gv[c]);
+        }
+      }
+      // d v_c / d x_m += (dr_k/dx_m) D_k v_c, symmetrised into the strain rows
+      const T g0 = gl[k * 3 + 0], g1 = gl[k * 3 + 1], g2 = gl[k * 3 + 2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        rhs[3][r] += g0 * gv[0][r];
+        rhs[4][r] += g1 * gv[1][r];
+        rhs[5][r] += g2 * gv[2][r];
+        rhs[6][r] += T(0.5) * (g2 * gv[1][r] + g1 * gv[2][r]);
+        rhs[7][r] += T(0.5) * (g2 * gv[0][r] + g0 * gv[2][r]);
+        rhs[8][r] += T(0.5) * (g1 * gv[0][r] + g0 * gv[1][r]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- interface corrections, one face at a time, lifted on the matrix cores
+  T* Sf = sY;  // [NfpK][144]
+  for (int x = tid; x < (NfpK - Nfp) * 144; x += NT) Sf[Nfp * 144 + x] = T(0);
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    T lf[KF];
+    if (own) {
+      const T* Lr = a.Lpad + ((f * RT + R) * KF) * 64 + l;
+#pragma unroll
+      for (int kk = 0; kk < KF; ++kk) lf[kk] = Lr[kk * 64];
+    }
+#pragma unroll
+    for (int p = 0; p < FPT; ++p) {
+      const int x = tid + p * NT;
+      if (x >= Nfp * E) continue;
+      const int e = x / Nfp, j = x % Nfp;
+      T* fl = &Sf[j * 144 + e];
+      if (e0 + e >= Ke) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) fl[c * 16] = T(0);
+        continue;
+      }
+      const int il = a.fmask[f * Nfp + j];
+      const T* gg = &sgeo[e * 32];
+      const T n[3] = {gg[9 + f * 4 + 0], gg[9 + f * 4 + 1], gg[9 + f * 4 + 2]};
+      const T fs = gg[9 + f * 4 + 3];
+      T vm[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vm[c] = Sv[il * 48 + c * 16 + e];
+      const T* sm = pf[p].sm;
+      const T* sp = pf[p].sp;
+      const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2], sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
+                       sm[4] * n[0] + sm[3] * n[1] + sm[2] * n[2]};
+      const T Tp[3] = {sp[0] * n[0] + sp[5] * n[1] + sp[4] * n[2], sp[5] * n[0] + sp[1] * n[1] + sp[3] * n[2],
+                       sp[4] * n[0] + sp[3] * n[1] + sp[2] * n[2]};
+      T dT[3], dv[3];
+      interface_state(n, vm, Tm, pf[p].vp, Tp, gg[25], pf[p].zp, gg[26], pf[p].zs, dT, dv);
+      fl[0 * 16] = fs * dT[0];
+      fl[1 * 16] = fs * dT[1];
+      fl[2 * 16] = fs * dT[2];
+      fl[3 * 16] = fs * n[0] * dv[0];
+      fl[4 * 16] = fs * n[1] * dv[1];
+      fl[5 * 16] = fs * n[2] * dv[2];
+      fl[6 * 16] = fs * T(0.5) * (n[1] * dv[2] + n[2] * dv[1]);
+      fl[7 * 16] = fs * T(0.5) * (n[0] * dv[2] + n[2] * dv[0]);
+      fl[8 * 16] = fs * T(0.5) * (n[0] * dv[1] + n[1] * dv[0]);
+    }
+    if (f < 3) gather(f + 1, pf);   // next face's loads overlap this face's lift
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int kk = 0; kk < KF; ++kk) {
+        const int row = (4 * kk + lg) * 144 + lr;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) rhs[c] = M::mma(lf[kk], Sf[row + c * 16], rhs[c]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- strain rows: update in registers, new strains to LDS for sigma_h;
+  // the velocity rows go to LDS for the per-element mass inverse.
+  T* Srv = sY;  // [NpK][48] (the face buffer is free after the lift)
+  T* Se = sX;   // [NpK][96]
+  if (own) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int m = 0; m < 3; ++m)
-        gr[c][m] = g[0 * 3 + m] * gv[c][0] + g[1 * 3 + m] * gv[c][1] + g[2 * 3 + m] * gv[c][2];
-    rhs[0] = div[0];
-    rhs[1] = div[1];
-    rhs[2] = div[2];
-    rhs[3] = gr[0][0];
-    rhs[4] = gr[1][1];
-    rhs[5] = gr[2][2];
-    rhs[6] = T(0.5) * (gr[1][2] + gr[2][1]);
-    rhs[7] = T(0.5) * (gr[0][2] + gr[2][0]);
-    rhs[8] = T(0.5) * (gr[0][1] + gr[1][0]);
+      for (int r = 0; r < 4; ++r) {
+        const int i = R * 16 + M::row(lg, r);
+        if (i < NpK) Srv[i * 48 + c * 16 + lr] = rhs[c][r];
+      }
+    const int ge = e0 + lr;
+    // all loads first, then the stores (res and q may not be proven disjoint
+    // by the compiler, which would otherwise serialise every round trip)
+    T rv[6][4], qv[6][4];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = R * 16 + M::row(lg, r);
+        rv[m][r] = T(0);
+        qv[m][r] = T(0);
+        if (MODE == 1 && i < Np && ge < Ke) {
+          const int idx = ge * 9 * Np + (3 + m) * Np + i;
+          rv[m][r] = a.out[idx];
+          qv[m][r] = a.qin[idx];
+        }
+      }
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = R * 16 + M::row(lg, r);
+        if (i >= NpK) continue;
+        T qn = T(0);
+        if (i < Np && ge < Ke) {
+          const int idx = ge * 9 * Np + (3 + m) * Np + i;
+          if (MODE == 0) {
+            a.out[idx] = rhs[3 + m][r];
+          } else {
+            const T rr = a.a * rv[m][r] + a.dt * rhs[3 + m][r];
+            qn = qv[m][r] + a.b * rr;
+            a.out[idx] = rr;
+            a.qout[idx] = qn;
+          }
+        }
+        Se[i * 96 + m * 16 + lr] = qn;
+      }
   }
   __syncthreads();
 
-  // Interface corrections at every face node, scaled by Fscale.
-  for (int x = tid; x < ne * NF; x += NT) {
-    const int ee = x / NF, fj = x % NF, f = fj / Nfp, j = fj % Nfp;
-    const int il = a.fmask[f * Nfp + j];
-    const T* gg = &sg[ee * 32];
-    const T n[3] = {gg[9 + f * 4 + 0], gg[9 + f * 4 + 1], gg[9 + f * 4 + 2]};
-    const T fs = gg[9 + f * 4 + 3];
-    T vm[3], sm[6], vp[3], sp[6];
+  // ---- density-weighted mass inverse on the velocity rows (per element)
+  for (int x = tid; x < E * Np; x += NT) {
+    const int e = x / Np, i = x % Np;
+    const int ge = e0 + e;
+    if (ge >= Ke) continue;
+    const T* Wm = a.W + ge * Np * Np + i;
+    T rv[3], qv[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vm[c] = sq[ee * 9 * Np + c * Np + il];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) sm[m] = ss[ee * 6 * Np + m * Np + il];
-    const int32_t w = a.conn[(e0 + ee) * 4 + f];
-    const int64_t nb = w >> 5;
-    const int code = w & 31;
-    const int nn = a.nbrnode[((f * 4 + code / 6) * 6 + code % 6) * Nfp + j];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) vp[c] = a.qin[nb * 9 * Np + c * Np + nn];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) sp[m] = a.sin[nb * 6 * Np + m * Np + nn];
-    const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2],
-                     sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
-                     sm[4] * n[0] + sm[3] * n[1] + sm[2] * n[2]};
-    const T Tp[3] = {sp[0] * n[0] + sp[5] * n[1] + sp[4] * n[2],
-                     sp[5] * n[0] + sp[1] * n[1] + sp[3] * n[2],
-                     sp[4] * n[0] + sp[3] * n[1] + sp[2] * n[2]};
-    T dT[3], dv[3];
-    interface_state(n, vm, Tm, vp, Tp, gg[25], a.Z[nb * 2], gg[26], a.Z[nb * 2 + 1], dT, dv);
-    T* fl = &sb[ee * BUF + fj];
-    fl[0 * NF] = fs * dT[0];
-    fl[1 * NF] = fs * dT[1];
-    fl[2 * NF] = fs * dT[2];
-    fl[3 * NF] = fs * n[0] * dv[0];
-    fl[4 * NF] = fs * n[1] * dv[1];
-    fl[5 * NF] = fs * n[2] * dv[2];
-    fl[6 * NF] = fs * T(0.5) * (n[1] * dv[2] + n[2] * dv[1]);
-    fl[7 * NF] = fs * T(0.5) * (n[0] * dv[2] + n[2] * dv[0]);
-    fl[8 * NF] = fs * T(0.5) * (n[0] * dv[1] + n[1] * dv[0]);
-  }
-  __syncthreads();
-
-  if (act) {
-    const T* fl = &sb[e * BUF];
-    for (int m = 0; m < NF; ++m) {
-      const T L = a.LIFTT[m * Np + i];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) rhs[c] += L * fl[c * NF + m];
+    for (int c = 0; c < 3; ++c) {
+      rv[c] = (MODE == 1) ? a.out[ge * 9 * Np + c * Np + i] : T(0);
+      qv[c] = (MODE == 1) ? a.qin[ge * 9 * Np + c * Np + i] : T(0);
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) sr[e * 3 * Np + c * Np + i] = rhs[c];
-  }
-  __syncthreads();
-
-  if (act) {
-    const int64_t ge = e0 + e;
-    const T* W = a.W + ge * Np * Np;
     T o0 = 0, o1 = 0, o2 = 0;
-    const T* r = &sr[e * 3 * Np];
+#pragma unroll 8
     for (int j = 0; j < Np; ++j) {
-      const T wv = W[j * Np + i];
-      o0 += wv * r[j];
-      o1 += wv * r[Np + j];
-      o2 += wv * r[2 * Np + j];
+      const T wv = Wm[j * Np];
+      o0 += wv * Srv[j * 48 + e];
+      o1 += wv * Srv[j * 48 + 16 + e];
+      o2 += wv * Srv[j * 48 + 32 + e];
     }
     if (ge == a.src_elem) {
       const T sv = a.srcval * a.svec[i];
@@ -238,55 +416,114 @@ __global__ __launch_bounds__((StageCfg<T, N>::NT)) void k_stage(StageArgs<T> a) 
       o1 += sv * a.dir1;
       o2 += sv * a.dir2;
     }
-    rhs[0] = o0;
-    rhs[1] = o1;
-    rhs[2] = o2;
-    if (MODE == 0) {
+    const T o[3] = {o0, o1, o2};
 #pragma unroll
-      for (int c = 0; c < 9; ++c) a.out[ge * 9 * Np + c * Np + i] = rhs[c];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        const int64_t idx = ge * 9 * Np + c * Np + i;
-        const T rr = a.a * a.out[idx] + a.dt * rhs[c];
+    for (int c = 0; c < 3; ++c) {
+      const int idx = ge * 9 * Np + c * Np + i;
+      if (MODE == 0) {
+        a.out[idx] = o[c];
+      } else {
+        const T rr = a.a * rv[c] + a.dt * o[c];
         a.out[idx] = rr;
-        const T qn = sq[e * 9 * Np + c * Np + i] + a.b * rr;
-        a.qout[idx] = qn;
-        sq[e * 9 * Np + c * Np + i] = qn;
+        a.qout[idx] = qv[c] + a.b * rr;
       }
     }
   }
   if (MODE == 0) return;
   __syncthreads();
 
-  // sigma_h of the new state: strains at the quadrature points, Hooke's law
-  // with the sampled lambda, mu, and the L2_Q projection back to the nodes.
-  for (int x = tid; x < ne * Nq; x += NT) {
-    const int ee = x / Nq, qp = x % Nq;
-    T ep[6] = {0, 0, 0, 0, 0, 0};
-    const T* qq = &sq[ee * 9 * Np + 3 * Np];
-    for (int j = 0; j < Np; ++j) {
-      const T vv = a.VqT[j * Nq + qp];
+  // ---- sigma_h of the new state: strains at the quadrature points (matrix
+  // cores), Hooke's law with the sampled lambda, mu, and the L2_Q projection
+  // back to the nodes, in chunks of at most 128 quadrature points.
+  T* Sq = sY;  // [QC][48]
+  constexpr int QC = TL::QC, NQC = (QT * 16 + QC - 1) / QC, MP = (RT * 3 + NW - 1) / NW;
+  constexpr int KQ = QC / 4;
+#pragma unroll 1
+  for (int ch = 0; ch < 2; ++ch) {
+    acc_t pq[MP];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) ep[m] += vv * qq[m * Np + j];
+    for (int s = 0; s < MP; ++s) pq[s] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
+    for (int qc = 0; qc < NQC; ++qc) {
+      const int q0 = qc * QC;
+      const int rows = (NqK - q0) < QC ? (NqK - q0) : QC;   // K rows of this chunk
+#pragma unroll 1
+      for (int Rq = q0 / 16 + w; Rq < QT && Rq * 16 < q0 + QC; Rq += NW) {
+        T vf[KD];
+        const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
+#pragma unroll
+        for (int kk = 0; kk < KD; ++kk) vf[kk] = Vr[kk * 64];
+        const int ge = e0 + lr;
+        // unconditional loads from clamped (valid) indices, masked after
+        const int gc = ge < Ke ? ge : Ke - 1;
+        T lam[4], mu2[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = Rq * 16 + M::row(lg, r);
+          const int qc = q < Nq ? q : Nq - 1;
+          lam[r] = a.lm[gc * 2 * Nq + qc];
+          mu2[r] = T(2) * a.lm[gc * 2 * Nq + Nq + qc];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const bool ok = Rq * 16 + M::row(lg, r) < Nq && ge < Ke;
+          lam[r] = ok ? lam[r] : T(0);
+          mu2[r] = ok ? mu2[r] : T(0);
+        }
+        acc_t ac[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) ac[m] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < KD; ++kk) {
+          const int row = (4 * kk + lg) * 96 + ch * 48 + lr;
+#pragma unroll
+          for (int m = 0; m < 3; ++m) ac[m] = M::mma(vf[kk], Se[row + m * 16], ac[m]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = Rq * 16 + M::row(lg, r);
+          if (q >= NqK) continue;
+          const T ltr = (ch == 0) ? lam[r] * (ac[0][r] + ac[1][r] + ac[2][r]) : T(0);
+          T* o = &Sq[(q - q0) * 48 + lr];
+          o[0] = mu2[r] * ac[0][r] + ltr;
+          o[16] = mu2[r] * ac[1][r] + ltr;
+          o[32] = mu2[r] * ac[2][r] + ltr;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < MP; ++s) {
+        const int p = w + s * NW;
+        if (p >= RT * 3) continue;
+        const int Ro = p / 3, m = p % 3;
+        __builtin_amdgcn_sched_barrier(0);   // keep each pair's fragment loads with its products
+        const T* Pr = a.Pqpad + (Ro * (NqK / 4) + q0 / 4) * 64 + l;
+        // fragments in groups of 8 k-steps: loads of a group issue together
+#pragma unroll
+        for (int k0 = 0; k0 < KQ; k0 += 8) {
+          T pf2[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pf2[u] = (k0 + u < KQ && 4 * (k0 + u) < rows) ? Pr[(k0 + u) * 64] : T(0);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k0 + u < KQ && 4 * (k0 + u) < rows)
+              pq[s] = M::mma(pf2[u], Sq[(4 * (k0 + u) + lg) * 48 + m * 16 + lr], pq[s]);
+        }
+      }
+      __syncthreads();
     }
-    const T lam = a.lm[(e0 + ee) * 2 * Nq + qp], mu = a.lm[(e0 + ee) * 2 * Nq + Nq + qp];
-    const T ltr = lam * (ep[0] + ep[1] + ep[2]);
-    T* o = &sb[ee * BUF + qp];
+    const int ge = e0 + lr;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) o[m * Nq] = T(2) * mu * ep[m] + (m < 3 ? ltr : T(0));
-  }
-  __syncthreads();
-  if (act) {
-    T sh[6] = {0, 0, 0, 0, 0, 0};
-    const T* sqp = &sb[e * BUF];
-    for (int qp = 0; qp < Nq; ++qp) {
-      const T pv = a.PqT[qp * Np + i];
+    for (int s = 0; s < MP; ++s) {
+      const int p = w + s * NW;
+      if (p >= RT * 3 || ge >= Ke) continue;
+      const int Ro = p / 3, m = p % 3;
 #pragma unroll
-      for (int m = 0; m < 6; ++m) sh[m] += pv * sqp[m * Nq + qp];
+      for (int r = 0; r < 4; ++r) {
+        const int i = Ro * 16 + M::row(lg, r);
+        if (i < Np) a.sout[ge * 6 * Np + (3 * ch + m) * Np + i] = pq[s][r];
+      }
     }
-#pragma unroll
-    for (int m = 0; m < 6; ++m) a.sout[(e0 + e) * 6 * Np + m * Np + i] = sh[m];
   }
 }
 
@@ -540,12 +777,10 @@ static StageArgs<T> stage_args(const Dev& d, const void* qin, const void* sin, v
   a.fgeo = static_cast<const T*>(d.fgeo);
   a.Z = static_cast<const T*>(d.Z);
   a.svec = static_cast<const T*>(d.svec);
-  a.DrT = static_cast<const T*>(d.DrT);
-  a.DsT = static_cast<const T*>(d.DsT);
-  a.DtT = static_cast<const T*>(d.DtT);
-  a.LIFTT = static_cast<const T*>(d.LIFTT);
-  a.VqT = static_cast<const T*>(d.VqT);
-  a.PqT = static_cast<const T*>(d.PqT);
+  a.Dpad = static_cast<const T*>(d.Dpad);
+  a.Lpad = static_cast<const T*>(d.Lpad);
+  a.Vqpad = static_cast<const T*>(d.Vqpad);
+  a.Pqpad = static_cast<const T*>(d.Pqpad);
   a.conn = d.conn;
   a.nbrnode = d.nbrnode;
   a.fmask = d.fmask;
@@ -564,13 +799,17 @@ static StageArgs<T> stage_args(const Dev& d, const void* qin, const void* sin, v
 template <typename T, int N>
 static hipError_t stage_impl(const Dev& d, int mode, const void* qin, const void* sin, void* qout,
                              void* sout, void* out, const StageCoef& c, hipStream_t st) {
-  using C = StageCfg<T, N>;
+  using TL = Tile<N>;
+  // the stage kernel indexes its arrays with 32-bit element offsets
+  if (d.K * 9 * TL::Np >= (int64_t(1) << 31) || d.K * TL::Np * TL::Np >= (int64_t(1) << 31) ||
+      d.K * 2 * TL::Nq >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
   const StageArgs<T> a = stage_args<T>(d, qin, sin, qout, sout, out, c);
-  const unsigned grid = static_cast<unsigned>((d.K + C::E - 1) / C::E);
+  const unsigned grid = static_cast<unsigned>((d.K + TL::E - 1) / TL::E);
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage<T, N, 0>), dim3(grid), dim3(C::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 0>), dim3(grid), dim3(TL::NT), 0, st, a);
   else
-    hipLaunchKernelGGL((k_stage<T, N, 1>), dim3(grid), dim3(C::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 1>), dim3(grid), dim3(TL::NT), 0, st, a);
   return hipGetLastError();
 }
 
