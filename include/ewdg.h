@@ -158,6 +158,22 @@ int ewdg_time(const ewdg_ctx* ctx, double* t);
  * with a deterministic reduction; synchronises. */
 int ewdg_energy(ewdg_ctx* ctx, double* E);
 
+/* Batched stepping of many independent contexts (continuous-batching
+ * serving).  Contexts are grouped by (degree, precision); every LSRK stage
+ * issues one ragged launch per group covering all elements of all its
+ * contexts, so the requests' work overlaps on the device while each
+ * context's arithmetic stays exactly that of ewdg_step (results are
+ * bitwise identical alone or in any mix).  dts[i] is context i's step; all
+ * advance nsteps steps, recording their receivers.  table_dev is caller-
+ * owned device memory of at least ewdg_batch_table_bytes(n) bytes holding
+ * the per-request launch table; all work is enqueued on hip_stream (the
+ * contexts' own streams are not used).  A context may appear only once.
+ * Errors are reported through the return code; the message of the failing
+ * context is in its ewdg_last_error. */
+int ewdg_batch_table_bytes(int n, size_t* bytes);
+int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps, void* table_dev,
+                    size_t table_bytes, void* hip_stream);
+
 const char* ewdg_last_error(const ewdg_ctx* ctx);
 
 #ifdef __cplusplus

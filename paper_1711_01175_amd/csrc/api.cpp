@@ -2,8 +2,10 @@
 // LSRK(5,4) driver.  Device work is enqueued on the context's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -613,6 +615,99 @@ int ewdg_energy(ewdg_ctx* c, double* E) {
   if ((rc = c->hip(launch_energy(c->d, c->d.q[c->cur], c->d.scal, c->stream), "energy"))) return rc;
   if ((rc = c->hip(hipMemcpyAsync(E, c->d.scal, 8, hipMemcpyDeviceToHost, c->stream), "energy copy"))) return rc;
   return c->hip(hipStreamSynchronize(c->stream), "energy sync");
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// Per step the table holds, for each of the 5 stages, n argument records
+// followed by the groups' tile prefix arrays.
+static size_t batch_record_bytes() {
+  const size_t s = std::max(stage_args_bytes(32), stage_args_bytes(64));
+  return (s + 15) / 16 * 16;
+}
+
+int ewdg_batch_table_bytes(int n, size_t* bytes) {
+  if (n < 0 || !bytes) return EWDG_EINVAL;
+  *bytes = 5 * (static_cast<size_t>(n) * batch_record_bytes() + 2 * static_cast<size_t>(n) * 4 + 256) + 256;
+  return EWDG_OK;
+}
+
+int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps, void* table_dev,
+                    size_t table_bytes, void* hip_stream) {
+  if (n < 0 || nsteps < 0 || (n > 0 && (!ctxs || !dts || !table_dev))) return EWDG_EINVAL;
+  if (n == 0 || nsteps == 0) return EWDG_OK;
+  size_t need_b = 0;
+  ewdg_batch_table_bytes(n, &need_b);
+  if (table_bytes < need_b) return EWDG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < n; ++i) {
+    ewdg_ctx* c = ctxs[i];
+    if (!c) return EWDG_EINVAL;
+    if (int rc = need(c, true, true, true)) return c->fail(rc, "step_batch needs material");
+    if (!(dts[i] > 0.0)) return c->fail(EWDG_EINVAL, "non-positive dt");
+    if (c->nr > 0 && c->rec_count + nsteps > c->max_steps)
+      return c->fail(EWDG_ENOMEM, "receiver record capacity exceeded");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return c->fail(EWDG_EINVAL, "context repeated in a batch");
+  }
+  // groups of (degree, precision), in a fixed order
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  for (int i = 0; i < n; ++i) groups[{ctxs[i]->N, ctxs[i]->prec}].push_back(i);
+  const size_t rec = batch_record_bytes();
+  const int E = stage_tile_elems();
+  std::vector<char> host(need_b, 0);
+  char* dev = static_cast<char*>(table_dev);
+  for (int step = 0; step < nsteps; ++step) {
+    // table for the five stages of this step
+    struct Launch { int N, prec, nreq, ntiles; size_t args_off, tiles_off; };
+    std::vector<Launch> launches;
+    size_t off = 0;
+    for (int i = 0; i < 5; ++i) {
+      const size_t stage_base = off;
+      size_t rec_off = stage_base, tiles_off = stage_base + static_cast<size_t>(n) * rec;
+      for (auto& g : groups) {
+        Launch L{g.first.first, g.first.second, static_cast<int>(g.second.size()), 0, rec_off, tiles_off};
+        int32_t* ts = reinterpret_cast<int32_t*>(&host[tiles_off]);
+        int tiles = 0;
+        for (size_t m = 0; m < g.second.size(); ++m) {
+          ewdg_ctx* c = ctxs[g.second[m]];
+          const double dt = dts[g.second[m]];
+          const int cur = (c->cur + i) & 1;
+          const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, c->t + kRkC[i] * dt);
+          stage_args_fill(c->d, c->d.q[cur], c->d.s[cur], c->d.q[1 - cur], c->d.s[1 - cur], c->d.res, sc,
+                          &host[rec_off]);
+          rec_off += rec;
+          ts[m] = tiles;
+          tiles += static_cast<int>((c->mesh.K + E - 1) / E);
+        }
+        ts[g.second.size()] = tiles;
+        L.ntiles = tiles;
+        launches.push_back(L);
+        tiles_off += (g.second.size() + 1) * 4;
+      }
+      off = (tiles_off + 255) / 256 * 256;
+    }
+    hipError_t e = hipMemcpyAsync(dev, host.data(), off, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return ctxs[0]->hip(e, "batch table copy");
+    for (const Launch& L : launches) {
+      e = launch_stage_batch(L.N, L.prec, dev + L.args_off, static_cast<int>(rec),
+                             reinterpret_cast<const int*>(dev + L.tiles_off), L.nreq, L.ntiles, st);
+      if (e != hipSuccess) return ctxs[0]->hip(e, "batched stage");
+    }
+    for (int i = 0; i < n; ++i) {
+      ewdg_ctx* c = ctxs[i];
+      c->cur = (c->cur + 5) & 1;
+      c->t = c->t + dts[i];
+      if (c->nr > 0) {
+        e = launch_receivers(c->d, c->d.q[c->cur], c->nr, c->rec_count, st);
+        if (e != hipSuccess) return c->hip(e, "receivers");
+        ++c->rec_count;
+      }
+    }
+  }
+  return EWDG_OK;
 }
 
 }  // extern "C"

@@ -75,4 +75,16 @@ hipError_t launch_receivers(const Dev& d, const void* q, int nr, int step, hipSt
 hipError_t launch_energy(const Dev& d, const void* q, double* out, hipStream_t st);
 bool supported_degree(int N);
 
+// Batched stages over many meshes of one degree and precision: a device
+// table of per-request stage arguments (filled on the host) and the first
+// workgroup of each request.
+size_t stage_args_bytes(int prec);
+void stage_args_fill(const Dev& d, const void* qin, const void* sin, void* qout, void* sout, void* out,
+                     const StageCoef& c, void* dst);
+int stage_tile_elems();
+// records in the table are record_bytes apart (a multiple of 16, at least
+// stage_args_bytes(prec))
+hipError_t launch_stage_batch(int N, int prec, const void* table, int record_bytes, const int* tile_start,
+                              int nreq, int ntiles, hipStream_t st);
+
 }  // namespace ewdg

@@ -141,7 +141,7 @@ struct FacePt {
 };
 
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage(StageArgs<T> a) {
+__device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   using TL = Tile<N>;
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
@@ -157,8 +157,7 @@ __global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage(StageArgs<T> a) {
   const int w = tid >> 6, l = tid & 63;
   const int lr = l & 15, lg = l >> 4;  // A row / B column; K sub-index
   const int Ke = static_cast<int>(a.K);
-  const int nblk = (Ke + E - 1) / E;
-  const int e0 = static_cast<int>(xcd_tile(blockIdx.x, nblk)) * E;
+  const int e0 = tile * E;
   const bool own = w < RT;             // this wave owns node row tile R = w
   const int R = w;
 
@@ -527,6 +526,33 @@ __global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage(StageArgs<T> a) {
   }
 }
 
+// One mesh: workgroups map to element tiles, XCD-contiguous.
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage(StageArgs<T> a) {
+  const int nblk = static_cast<int>((a.K + Tile<N>::E - 1) / Tile<N>::E);
+  stage_body<T, N, MODE>(a, static_cast<int>(xcd_tile(blockIdx.x, nblk)));
+}
+
+// Many independent meshes of the same degree in one ragged launch: request r
+// owns workgroups [tile_start[r], tile_start[r+1]); each request's arithmetic
+// is exactly that of its own single-mesh launch.
+template <typename T, int N>
+__global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage_batch(const char* __restrict__ table,
+                                                                   int record_bytes,
+                                                                   const int* __restrict__ tile_start,
+                                                                   int nreq) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nreq;   // largest r with tile_start[r] <= b
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (tile_start[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  // records are record_bytes apart (the host lays out both precisions alike)
+  const StageArgs<T> a = *reinterpret_cast<const StageArgs<T>*>(table + static_cast<size_t>(lo) * record_bytes);
+  stage_body<T, N, 1>(a, b - tile_start[lo]);
+}
+
 // sigma_h = P_Q(lambda tr(e) I + 2 mu e) for a given state (no update).
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_sigma(const T* __restrict__ q, T* __restrict__ s,
@@ -834,6 +860,23 @@ static hipError_t material_impl(const Dev& d, hipStream_t st) {
   return hipSuccess;
 }
 
+template <typename T, int N>
+static hipError_t stage_batch_impl(const void* table, int record_bytes, const int* tile_start, int nreq,
+                                   int ntiles, hipStream_t st) {
+  using TL = Tile<N>;
+  if (ntiles <= 0) return hipSuccess;
+  if (record_bytes < static_cast<int>(sizeof(StageArgs<T>)) || record_bytes % 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_stage_batch<T, N>), dim3(static_cast<unsigned>(ntiles)), dim3(TL::NT), 0, st,
+                     static_cast<const char*>(table), record_bytes, tile_start, nreq);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void fill_args(const Dev& d, const void* qin, const void* sin, void* qout, void* sout, void* out,
+                      const StageCoef& c, void* dst) {
+  *static_cast<StageArgs<T>*>(dst) = stage_args<T>(d, qin, sin, qout, sout, out, c);
+}
+
 #define EWDG_DISPATCH(NVAL, CALL)       \
   switch (NVAL) {                       \
     case 1: { constexpr int NN = 1; CALL; } \
@@ -936,4 +979,24 @@ hipError_t launch_energy(const Dev& d, const void* q, double* out, hipStream_t s
   return hipGetLastError();
 }
 
+}  // namespace ewdg
+
+namespace ewdg {
+size_t stage_args_bytes(int prec) { return prec == 32 ? sizeof(StageArgs<float>) : sizeof(StageArgs<double>); }
+
+void stage_args_fill(const Dev& d, const void* qin, const void* sin, void* qout, void* sout, void* out,
+                     const StageCoef& c, void* dst) {
+  if (d.prec == 32) fill_args<float>(d, qin, sin, qout, sout, out, c, dst);
+  else fill_args<double>(d, qin, sin, qout, sout, out, c, dst);
+}
+
+int stage_tile_elems() { return 16; }
+
+hipError_t launch_stage_batch(int N, int prec, const void* table, int record_bytes, const int* tile_start,
+                              int nreq, int ntiles, hipStream_t st) {
+  if (prec == 32) {
+    EWDG_DISPATCH(N, return (stage_batch_impl<float, NN>(table, record_bytes, tile_start, nreq, ntiles, st)));
+  }
+  EWDG_DISPATCH(N, return (stage_batch_impl<double, NN>(table, record_bytes, tile_start, nreq, ntiles, st)));
+}
 }  // namespace ewdg

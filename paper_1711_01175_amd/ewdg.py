@@ -53,6 +53,8 @@ SIGNATURES = {
     "ewdg_step": [_c_p, _c_d, _c_i],
     "ewdg_time": [_c_p, _P_d],
     "ewdg_energy": [_c_p, _P_d],
+    "ewdg_batch_table_bytes": [_c_i, ctypes.POINTER(_c_sz)],
+    "ewdg_step_batch": [ctypes.POINTER(_c_p), _c_i, ctypes.POINTER(_c_d), _c_i, _c_p, _c_sz, _c_p],
     "ewdg_last_error": [_c_p],
 }
 _RESTYPE = {"ewdg_last_error": ctypes.c_char_p}
@@ -297,3 +299,27 @@ class Context:
         e = _c_d()
         self._check(self.lib.ewdg_energy(self.h, ctypes.byref(e)), "energy")
         return e.value
+
+
+def batch_table_bytes(n):
+    b = _c_sz()
+    rc = load().ewdg_batch_table_bytes(int(n), ctypes.byref(b))
+    if rc != EWDG_OK:
+        raise EwdgError(rc, "batch_table_bytes")
+    return b.value
+
+
+def step_batch(contexts, dts, nsteps, table, stream=None):
+    """ewdg_step_batch over Context objects; table is a torch device buffer
+    of at least batch_table_bytes(len(contexts)) bytes."""
+    n = len(contexts)
+    if n == 0:
+        return
+    hs = (_c_p * n)(*[c.h for c in contexts])
+    d = (_c_d * n)(*[float(x) for x in dts])
+    rc = load().ewdg_step_batch(hs, n, d, int(nsteps), _ptr(table), table.numel() * table.element_size(),
+                                _c_p(stream))
+    if rc != EWDG_OK:
+        msgs = "; ".join(c.lib.ewdg_last_error(c.h).decode() for c in contexts
+                         if c.lib.ewdg_last_error(c.h))
+        raise EwdgError(rc, "step_batch " + msgs)

@@ -1,0 +1,185 @@
+"""Continuous-batching server for many independent forward solves.
+
+Requests (a mesh, degree, medium, source and step count each) arrive over
+time.  A request is admitted as soon as a slot is free and its exact device
+footprint (ewdg_workspace_bytes) fits in the remaining HBM budget; its state
+then stays on the device until it retires.  All admitted requests advance
+together through ewdg_step_batch: each LSRK stage is one ragged launch per
+degree class over every active request's elements, so requests that arrive
+while others run join the same launches at the next chunk boundary.  Each
+request's arithmetic is identical to a solo run, so results do not depend on
+the mix.
+
+Only orchestration lives here; every step of the method runs in libewdg.
+"""
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import ewdg as B
+
+
+def admit_fifo(waiting, n_active, used_bytes, slots, budget):
+    """First-in first-out admission.
+
+    waiting: sequence of (key, footprint_bytes).  Returns (admitted keys,
+    rejected keys): a request is admitted while a slot is free and its
+    footprint fits in the remaining budget; the head of the queue blocks the
+    ones behind it.  A request larger than the whole budget is rejected.
+    """
+    admitted, rejected = [], []
+    free_slots = slots - n_active
+    free_bytes = budget - used_bytes
+    for key, fp in waiting:
+        if fp > budget:
+            rejected.append(key)
+            continue
+        if free_slots <= 0 or fp > free_bytes:
+            break
+        admitted.append(key)
+        free_slots -= 1
+        free_bytes -= fp
+    return admitted, rejected
+
+
+@dataclass
+class _Live:
+    req: object
+    ctx: object
+    footprint: int
+    dt: float = 0.0
+    done: int = 0
+    t_admit: float = 0.0
+    ws: object = None
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    latency: float
+    K: int
+    N: int
+    nsteps: int
+    energy: float
+    traces: np.ndarray
+    state: object = None
+
+
+@dataclass
+class ServeStats:
+    results: list = field(default_factory=list)
+    rejected: list = field(default_factory=list)
+    makespan: float = 0.0
+    dof_stages: float = 0.0
+    max_used_bytes: int = 0
+    max_active: int = 0
+
+    def latencies(self):
+        return np.array([r.latency for r in self.results])
+
+    def summary(self):
+        lat = self.latencies()
+        return {
+            "requests": len(self.results),
+            "rejected": len(self.rejected),
+            "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "makespan_s": self.makespan,
+            "GDOF_per_s": self.dof_stages / self.makespan / 1e9 if self.makespan > 0 else None,
+        }
+
+
+class Server:
+    """Admission by HBM footprint, continuous batching, per-request results."""
+
+    def __init__(self, budget_bytes, slots=32, precision=32, chunk_steps=10, cfl=0.5,
+                 keep_state=False):
+        import torch
+        self.torch = torch
+        self.budget = int(budget_bytes)
+        self.slots = int(slots)
+        self.precision = int(precision)
+        self.chunk = int(chunk_steps)
+        self.cfl = float(cfl)
+        self.keep_state = keep_state
+        self.stream = torch.cuda.current_stream()
+        self.table = torch.empty(B.batch_table_bytes(self.slots), dtype=torch.uint8, device="cuda")
+
+    def _prepare(self, req):
+        ctx = B.Context(req.N, self.precision, stream=self.stream.cuda_stream)
+        ctx.set_mesh(*req.mesh())
+        nr = len(req.receivers)
+        return _Live(req, ctx, ctx.workspace_bytes(nr, req.nsteps))
+
+    def _start(self, live, now):
+        req, ctx = live.req, live.ctx
+        nr = len(req.receivers)
+        live.ws = ctx.bind_workspace(nr, req.nsteps)
+        ctx.set_material(*req.material(ctx.quadrature_points()))
+        ctx.set_source(req.xs, req.direction, 1.0, req.f0, req.t0)
+        if nr:
+            ctx.set_receivers(req.receivers)
+        live.dt = ctx.cfl_dt(self.cfl)
+        live.t_admit = now
+
+    def _finish(self, live, now, stats):
+        req, ctx = live.req, live.ctx
+        traces = ctx.receivers() if len(req.receivers) else np.zeros((0, 0, 3))
+        state = ctx.get_state().cpu().numpy() if self.keep_state else None
+        stats.results.append(Result(req.rid, req.arrival, live.t_admit, now, now - req.arrival, ctx.K,
+                                    req.N, req.nsteps, ctx.energy(), traces, state))
+        stats.dof_stages += ctx.K * ctx.Np * 9 * 5 * req.nsteps
+        ctx.close()
+        live.ws = None
+
+    def run(self, requests, clock=time.perf_counter, sleep=time.sleep):
+        """Serve requests arriving at req.arrival seconds after the start."""
+        stats = ServeStats()
+        pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting, active = deque(), []
+        used = 0
+        t0 = clock()
+        while pending or waiting or active:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(self._prepare(pending.popleft()))
+            adm, rej = admit_fifo([(id(w), w.footprint) for w in waiting], len(active), used,
+                                  self.slots, self.budget)
+            for key in rej:
+                w = next(x for x in waiting if id(x) == key)
+                waiting.remove(w)
+                stats.rejected.append(w.req.rid)
+                w.ctx.close()
+            for key in adm:
+                w = next(x for x in waiting if id(x) == key)
+                waiting.remove(w)
+                self._start(w, clock() - t0)
+                used += w.footprint
+                active.append(w)
+            stats.max_used_bytes = max(stats.max_used_bytes, used)
+            stats.max_active = max(stats.max_active, len(active))
+            if not active:
+                if pending:
+                    sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.01)))
+                continue
+            chunk = min(self.chunk, min(a.req.nsteps - a.done for a in active))
+            B.step_batch([a.ctx for a in active], [a.dt for a in active], chunk, self.table,
+                         self.stream.cuda_stream)
+            self.stream.synchronize()
+            now = clock() - t0
+            still = []
+            for a in active:
+                a.done += chunk
+                if a.done >= a.req.nsteps:
+                    self._finish(a, now, stats)
+                    used -= a.footprint
+                else:
+                    still.append(a)
+            active = still
+        stats.makespan = clock() - t0
+        return stats

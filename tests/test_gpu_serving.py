@@ -1,0 +1,86 @@
+"""GPU checks of batched stepping and the continuous-batching server.
+
+Each request's result must be the same alone and in any mix: the batched
+launch runs exactly the per-request arithmetic of a solo ewdg_step, so the
+comparison is bitwise.  ewdg_step itself is pinned to the oracle by the
+parity tests.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+from workloads.requests import Request, request_stream
+
+pytestmark = pytest.mark.gpu
+
+
+def _solo(req, precision, nsteps):
+    import paper_1711_01175_amd as P
+    c = P.Context(req.N, precision)
+    c.set_mesh(*req.mesh())
+    c.bind_workspace()
+    c.set_material(*req.material(c.quadrature_points()))
+    c.set_source(req.xs, req.direction, 1.0, req.f0, req.t0)
+    dt = c.cfl_dt(0.5)
+    c.step(dt, nsteps)
+    return c.get_state().cpu().numpy(), c
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_step_batch_equals_solo(precision):
+    import paper_1711_01175_amd as P
+    reqs = request_stream(5, n_range=(3, 5), degrees=(2, 3, 4, 5), nsteps=12, seed0=40)
+    solo = [_solo(r, precision, 12)[0] for r in reqs]
+    ctxs, dts = [], []
+    for r in reqs:
+        c = P.Context(r.N, precision)
+        c.set_mesh(*r.mesh())
+        c.bind_workspace()
+        c.set_material(*r.material(c.quadrature_points()))
+        c.set_source(r.xs, r.direction, 1.0, r.f0, r.t0)
+        ctxs.append(c)
+        dts.append(c.cfl_dt(0.5))
+    table = torch.empty(P.batch_table_bytes(len(ctxs)), dtype=torch.uint8, device="cuda")
+    P.step_batch(ctxs, dts, 5, table)
+    P.step_batch(ctxs, dts, 7, table)
+    torch.cuda.synchronize()
+    print("degrees", [r.N for r in reqs], "sizes", [c.K for c in ctxs], flush=True)
+    for c, ref in zip(ctxs, solo):
+        assert np.array_equal(c.get_state().cpu().numpy(), ref)
+    assert all(abs(c.time() - 12 * dt) < 1e-12 for c, dt in zip(ctxs, dts))
+
+
+def test_server_continuous_batching_alone_vs_mix():
+    from paper_1711_01175_amd.serving import Server
+    reqs = request_stream(7, n_range=(3, 5), degrees=(2, 3, 4), nsteps=20, seed0=77)
+    # all queued at t = 0 with 3 slots and different lengths: queued requests
+    # are admitted at chunk boundaries while others are still mid-run
+    for i, r in enumerate(reqs):
+        r.nsteps = 12 + 8 * (i % 3)
+    rec = np.array([[0.1, 0.2, -0.3], [-0.7, 0.0, 0.4]])
+    for r in reqs:
+        r.receivers = rec
+    fps = []
+    import paper_1711_01175_amd as P
+    for r in reqs:
+        c = P.Context(r.N, 32)
+        c.set_mesh(*r.mesh())
+        fps.append(c.workspace_bytes(len(rec), r.nsteps))
+    budget = int(2.5 * max(fps))
+    srv = Server(budget_bytes=budget, slots=3, precision=32, chunk_steps=4, keep_state=True)
+    stats = srv.run(reqs)
+    print(stats.summary(), "max_active", stats.max_active, flush=True)
+    assert len(stats.results) == len(reqs) and not stats.rejected
+    assert stats.max_used_bytes <= budget and stats.max_active <= 3
+    by = {r.rid: r for r in stats.results}
+    # some request was admitted while another was still running
+    overlap = any(a.admitted < b.finished and a.admitted > b.admitted
+                  for a in stats.results for b in stats.results if a.rid != b.rid)
+    assert overlap
+    for r in reqs:
+        alone = Server(budget_bytes=budget, slots=1, precision=32, chunk_steps=7, keep_state=True)
+        r2 = Request(r.rid, r.n, r.N, r.nsteps, r.xs, r.phases, r.amps, 0.0, r.direction, r.f0, r.t0, rec)
+        res = alone.run([r2]).results[0]
+        assert np.array_equal(res.state, by[r.rid].state)
+        assert np.array_equal(res.traces, by[r.rid].traces)
+        assert res.traces.shape == (r.nsteps, len(rec), 3) and np.abs(res.traces).max() > 0

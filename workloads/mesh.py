@@ -37,30 +37,26 @@ def kuhn_periodic_mesh(n, shuffle_seed=None):
     """
     h = 2.0 / n
     K = 6 * n ** 3
-    lat = np.zeros((K, 4, 3), dtype=np.int64)
-    e = 0
-    for k in range(n):
-        for j in range(n):
-            for i in range(n):
-                o = np.array([i, j, k], dtype=np.int64)
-                for p in _PERMS:
-                    pts = [o.copy()]
-                    cur = o.copy()
-                    for ax in p:
-                        cur = cur.copy()
-                        cur[ax] += 1
-                        pts.append(cur)
-                    if _orient(p) < 0:
-                        pts[2], pts[3] = pts[3], pts[2]
-                    lat[e] = np.array(pts)
-                    e += 1
+    # hexahedron origins, x fastest: index = i + n (j + n k)
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    org = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=-1)            # [n^3][3]
+    tets = np.zeros((6, 4, 3), dtype=np.int64)
+    for t, p in enumerate(_PERMS):
+        cur = np.zeros(3, dtype=np.int64)
+        pts = [cur.copy()]
+        for ax in p:
+            cur[ax] += 1
+            pts.append(cur.copy())
+        if _orient(p) < 0:
+            pts[2], pts[3] = pts[3], pts[2]
+        tets[t] = np.array(pts)
+    lat = (org[:, None, None, :] + tets[None, :, :, :]).reshape(K, 4, 3)
     if shuffle_seed is not None:
         rng = np.random.default_rng(shuffle_seed)
-        even = [q for q in itertools.permutations(range(4))
-                if np.linalg.det(np.eye(4)[list(q)]) > 0]
+        even = np.array([q for q in itertools.permutations(range(4))
+                         if np.linalg.det(np.eye(4)[list(q)]) > 0])
         choice = rng.integers(0, len(even), size=K)
-        for e in range(K):
-            lat[e] = lat[e][list(even[choice[e]])]
+        lat = np.take_along_axis(lat, even[choice][:, :, None], axis=1)
     wrapped = lat % n
     EToV = wrapped[..., 0] + n * (wrapped[..., 1] + n * wrapped[..., 2])
     VXYZ = -1.0 + h * lat.astype(np.float64)
