@@ -39,7 +39,7 @@ VOIGT = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
 
 def _full(s6):
     """Voigt-ordered symmetric components [..., 6, X] -> [..., 3, 3, X]."""
-    out = np.empty(s6.shape[:-2] + (3, 3) + s6.shape[-1:])
+    out = np.empty(s6.shape[:-2] + (3, 3) + s6.shape[-1:], dtype=s6.dtype)
     for m, (i, j) in enumerate(VOIGT):
         out[..., i, j, :] = s6[..., m, :]
         out[..., j, i, :] = s6[..., m, :]
@@ -77,10 +77,14 @@ class Elastic:
         self.N, self.Np, self.Nq, self.K = N, R.Np, R.Nq, M.K
         if M.check_face_points(R.face_bary) > 1e-12:
             raise ValueError("inconsistent face matching")
-        self.rho_q = np.asarray(rho_q, dtype=np.float64).reshape(self.K, self.Nq)
-        self.lam_q = np.asarray(lam_q, dtype=np.float64).reshape(self.K, self.Nq)
-        self.mu_q = np.asarray(mu_q, dtype=np.float64).reshape(self.K, self.Nq)
-        if min(self.rho_q.min(), self.mu_q.min()) <= 0 or self.lam_q.min() < 0:
+        # real FP64 normally; complex values are accepted so that derivatives
+        # can be taken by the complex-step method
+        dt_ = np.result_type(np.asarray(rho_q).dtype, np.asarray(lam_q).dtype,
+                             np.asarray(mu_q).dtype, np.float64)
+        self.rho_q = np.asarray(rho_q, dtype=dt_).reshape(self.K, self.Nq)
+        self.lam_q = np.asarray(lam_q, dtype=dt_).reshape(self.K, self.Nq)
+        self.mu_q = np.asarray(mu_q, dtype=dt_).reshape(self.K, self.Nq)
+        if min(self.rho_q.real.min(), self.mu_q.real.min()) <= 0 or self.lam_q.real.min() < 0:
             raise ValueError("material must satisfy rho, mu > 0, lambda >= 0")
         w = R.wq
         # Density-weighted mass M_rho[k] = J_k (rho psi_m, psi_n)_Q.
@@ -159,10 +163,11 @@ class Elastic:
         M = self.mesh
         E = len(elems)
         P = self.ref.Nfq
-        vm = np.empty((E, 4, P, 3))
-        Tm = np.empty((E, 4, P, 3))
-        vp = np.empty((E, 4, P, 3))
-        Tp = np.empty((E, 4, P, 3))
+        dt_ = np.result_type(c.dtype, s.dtype)
+        vm = np.empty((E, 4, P, 3), dtype=dt_)
+        Tm = np.empty((E, 4, P, 3), dtype=dt_)
+        vp = np.empty((E, 4, P, 3), dtype=dt_)
+        Tp = np.empty((E, 4, P, 3), dtype=dt_)
         n = M.normal[elems]                                     # [E][4][3]
         for f in range(4):
             psi = self.own_psi[f]
@@ -227,7 +232,7 @@ class Elastic:
         be = sum(_apply(self.own_psi[f].T, np.swapaxes(wts[:, f, :, None] * de[:, f], 1, 2))
                  for f in range(4))
         J = M.J[elems]
-        out = np.empty((len(elems), 9, self.Np))
+        out = np.empty((len(elems), 9, self.Np), dtype=np.result_type(c.dtype, s.dtype, self.Mrho_inv.dtype))
         rv = J[:, None, None] * div + bv                           # [E][3][Np]
         out[:, 0:3] = np.swapaxes(self.Mrho_inv[elems] @ np.swapaxes(rv, 1, 2), 1, 2)
         out[:, 3:9] = symg + be / J[:, None, None]

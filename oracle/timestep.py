@@ -64,7 +64,7 @@ def run(op, c, dt, nsteps, t=0.0, source=None, receivers=None, callback=None):
     if receivers is not None:
         rec_loc = [op.locate(x) for x in np.atleast_2d(receivers)]
         rec_phi = [op.ref.basis.eval(rh[None, :])[0] for (_, rh) in rec_loc]
-        traces = np.zeros((nsteps, len(rec_loc), 3))
+        traces = np.zeros((nsteps, len(rec_loc), 3), dtype=c.dtype)
     for n in range(nsteps):
         for i in range(5):
             ts = t + C[i] * dt
