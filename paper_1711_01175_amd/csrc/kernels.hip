@@ -5,18 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include "dev.hpp"
+#include "kcommon.hpp"
 
 namespace ewdg {
 
-template <int N>
-struct Sz {
-  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
-  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
-  static constexpr int Nq = (N + 1) * (N + 1) * (N + 1);
-  static constexpr int NF = 4 * Nfp;
-  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
-  static constexpr int BUF = cmax(9 * Np, cmax(9 * NF, 6 * Nq));
-};
 
 // ---------------------------------------------------------------- MFMA tiles
 // 16x16x4 matrix-core tiles: C[16x16] += A[16x4] B[4x16].  Lane l supplies
@@ -876,17 +868,6 @@ static void fill_args(const Dev& d, const void* qin, const void* sin, void* qout
                       const StageCoef& c, void* dst) {
   *static_cast<StageArgs<T>*>(dst) = stage_args<T>(d, qin, sin, qout, sout, out, c);
 }
-
-#define EWDG_DISPATCH(NVAL, CALL)       \
-  switch (NVAL) {                       \
-    case 1: { constexpr int NN = 1; CALL; } \
-    case 2: { constexpr int NN = 2; CALL; } \
-    case 3: { constexpr int NN = 3; CALL; } \
-    case 4: { constexpr int NN = 4; CALL; } \
-    case 5: { constexpr int NN = 5; CALL; } \
-    case 7: { constexpr int NN = 7; CALL; } \
-    default: return hipErrorInvalidValue; \
-  }
 
 bool supported_degree(int N) { return N == 1 || N == 2 || N == 3 || N == 4 || N == 5 || N == 7; }
 
