@@ -174,6 +174,48 @@ int ewdg_batch_table_bytes(int n, size_t* bytes);
 int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps, void* table_dev,
                     size_t table_bytes, void* hip_stream);
 
+/* ---------------------------------------------------------------- adjoint
+ * Discrete adjoint of the fully discrete solve for the receiver misfit
+ *     J = 1/2 dt sum_{n=1..nsteps} sum_r |v_h(x_r, t_n) - d_r(t_n)|^2
+ * (traces after every step), with respect to per-element multipliers
+ * theta_e = (s_rho, s_lambda, s_mu) of the quadrature-sampled fields at
+ * theta = 1, i.e. g_e = dJ/d s applied to the current material (the
+ * impedances follow the element means; dt is held fixed).  The adjoint is
+ * the exact transpose of the discrete operator and of the LSRK(5,4)
+ * recurrence, so g is the derivative of the computed J up to rounding.
+ *
+ * ewdg_adjoint_workspace_bytes: size of a second caller-owned workspace for
+ * at most max_steps recorded steps with a checkpoint of (q, sigma_h) every
+ * checkpoint_every steps; it holds ceil(max_steps/checkpoint_every)
+ * checkpoints plus checkpoint_every step-start states of one segment, about
+ * (ceil(max_steps/C) + C + 13) * 15 K Np values in the run precision.  Call
+ * after ewdg_bind_workspace (the receiver capacity is taken from it);
+ * binding the forward workspace again or a new mesh drops the binding. */
+int ewdg_adjoint_workspace_bytes(const ewdg_ctx* ctx, int max_steps, int checkpoint_every, size_t* bytes);
+int ewdg_bind_adjoint_workspace(ewdg_ctx* ctx, void* device_ptr, size_t bytes, int max_steps,
+                                int checkpoint_every);
+/* LTy_dev = L^T y (the transpose of ewdg_rhs's linear part in the plain
+ * Euclidean product of nodal arrays [K][9][Np], context precision).  If
+ * g_dev (FP64 [K][3], device) is given, q_dev is required and
+ * g = y . d(L q + f(t))/d theta_e per element (rho, lambda, mu), computed
+ * at the state q_dev.  Outputs are overwritten.  Needs the adjoint
+ * workspace; does not change the stored state. */
+int ewdg_rhs_adjoint(ewdg_ctx* ctx, double t, const void* q_dev, const void* y_dev, void* LTy_dev,
+                     double* g_dev);
+/* Run nsteps steps of size dt from the stored state exactly as ewdg_step
+ * does, restarting the receiver record, checkpointing (q, sigma_h) every
+ * checkpoint_every steps, and return J for data[nsteps][nr][3] (host,
+ * FP64).  The stored state ends advanced by nsteps steps.  Changing the
+ * material, the source or the receivers discards the recorded run. */
+int ewdg_forward_misfit(ewdg_ctx* ctx, double dt, int nsteps, const double* data, double* J);
+/* Reverse sweep over the run recorded by ewdg_forward_misfit: recomputes
+ * each segment from its checkpoint, then applies the transposed stages
+ * in reverse.  g receives dJ/dtheta as FP64 [K][3] (rho, lambda, mu);
+ * qbar0, if not NULL, receives dJ/dq at the initial state ([K][9][Np],
+ * context precision).  Either pointer may be host or device memory.
+ * Synchronises. */
+int ewdg_adjoint_gradient(ewdg_ctx* ctx, double* g, void* qbar0);
+
 const char* ewdg_last_error(const ewdg_ctx* ctx);
 
 #ifdef __cplusplus

@@ -1,0 +1,43 @@
+// Device views of the adjoint workspace and the adjoint launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "dev.hpp"
+
+namespace ewdg {
+
+// Pointers into the caller's adjoint workspace ("run precision" as in Dev).
+struct AdjDev {
+  void* ytil = nullptr;      // [K][3][Np] W^T applied to the velocity adjoint
+  void* fown = nullptr;      // [K][4][Nfp][8] own-side face sensitivities
+  void* fnbr = nullptr;      // [K][4][Nfp][8] neighbour-side face sensitivities
+  void* qbar = nullptr;      // [K][9][Np] adjoint of the state
+  void* rbar = nullptr;      // [K][9][Np] adjoint of the LSRK register
+  void* rhs = nullptr;       // [K][9][Np] L q + f of the current stage input
+  void* res = nullptr;       // [K][9][Np] LSRK register of the recomputation
+  double* g = nullptr;       // [K][3] parameter gradient
+  double* resid = nullptr;   // [nsteps][nr][3] receiver residuals
+  // snapshots of (q, sigma_h(q)): checkpoints, step starts of one segment and
+  // the stage inputs of one step
+  void* ck_q = nullptr;      // [nck][K][9][Np]
+  void* ck_s = nullptr;      // [nck][K][6][Np]
+  void* seg_q = nullptr;     // [C][K][9][Np]
+  void* seg_s = nullptr;     // [C][K][6][Np]
+  void* st_q = nullptr;      // [5][K][9][Np] (q_1..q_5 of one step)
+  void* st_s = nullptr;      // [5][K][6][Np]
+};
+
+// qbar += scale * L^T y; if q is given also g += scale * y . d(L q + f)/d theta
+// (s = sigma_h(q), rhs = L q + f).
+hipError_t launch_adjoint(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
+                          const void* rhs, void* qbar, double* g, double scale, hipStream_t st);
+// qbar_v += scale * (receiver basis row)^T resid for every receiver
+hipError_t launch_adj_receivers(const Dev& d, void* qbar, const double* resid, int nr, double scale,
+                                hipStream_t st);
+hipError_t launch_axpy(int prec, void* y, const void* x, double a, int64_t n, hipStream_t st);
+hipError_t launch_scal(int prec, void* y, double a, int64_t n, hipStream_t st);
+
+}  // namespace ewdg

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "adjdev.hpp"
 #include "dev.hpp"
 #include "ewdg.h"
 #include "mesh.hpp"
@@ -51,6 +52,14 @@ struct ewdg_ctx {
   int64_t src_elem = -1;
   double src_dir[3] = {0, 0, 0}, src_amp = 0, src_f0 = 0, src_t0 = 0;
   int nr = 0, rec_count = 0;
+  // adjoint: workspace binding and the last recorded forward run
+  AdjDev ad;
+  bool adj_bound = false;
+  int adj_max_steps = 0, adj_every = 0, adj_rec = 0;
+  bool fwd_done = false;
+  int fwd_steps = 0;
+  double fwd_dt = 0.0;
+  std::vector<double> step_t;  // time at the start of every recorded step
   std::string err;
 
   size_t tsz() const { return prec == 32 ? 4 : 8; }
@@ -112,6 +121,10 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.Pqpad = take((NpR / 16) * (NqK / 4) * 64 * ts);
   d.VqT = take(Nq * Np * ts);
   d.PqT = take(Nq * Np * ts);
+  d.Dk = take(3 * Np * Np * ts);
+  d.LIFTr = take(4 * Nfp * Np * ts);
+  d.Vqr = take(Nq * Np * ts);
+  d.Pqr = take(Nq * Np * ts);
   d.Vq64T = reinterpret_cast<double*>(take(Nq * Np * 8));
   d.Pq64T = reinterpret_cast<double*>(take(Nq * Np * 8));
   d.Mhat64 = reinterpret_cast<double*>(take(Np * Np * 8));
@@ -120,6 +133,7 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.lam64 = reinterpret_cast<double*>(take(Nq * K * 8));
   d.mu64 = reinterpret_cast<double*>(take(Nq * K * 8));
   d.J64 = reinterpret_cast<double*>(take(K * 8));
+  d.means64 = reinterpret_cast<double*>(take(3 * K * 8));
   d.epart = reinterpret_cast<double*>(take(K * 8));
   d.scal = reinterpret_cast<double*>(take(64 * 8));
   d.srcb = reinterpret_cast<double*>(take(Np * 8));
@@ -130,6 +144,7 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.rec_out = reinterpret_cast<double*>(take(ms * mr * 3 * 8));
   d.conn = reinterpret_cast<int32_t*>(take(4 * K * 4));
   d.nbrnode = reinterpret_cast<int32_t*>(take(96 * Nfp * 4));
+  d.nbrface = reinterpret_cast<int32_t*>(take(96 * Nfp * 4));
   d.fmask = reinterpret_cast<int32_t*>(take(4 * Nfp * 4));
   return off;
 }
@@ -231,6 +246,8 @@ int ewdg_set_mesh(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* VXY
   c->has_mesh = true;
   c->bound = false;
   c->has_material = false;
+  c->adj_bound = false;
+  c->fwd_done = false;
   c->d.K = K;
   return EWDG_OK;
 }
@@ -380,6 +397,15 @@ int ewdg_bind_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_receivers,
   }
   if ((rc = upload_run(c, c->d.VqT, transpose(re.Vq, Nq, Np)))) return rc;
   if ((rc = upload_run(c, c->d.PqT, transpose(re.Pq, Np, Nq)))) return rc;
+  {
+    std::vector<double> Dk(re.Dr);
+    Dk.insert(Dk.end(), re.Ds.begin(), re.Ds.end());
+    Dk.insert(Dk.end(), re.Dt.begin(), re.Dt.end());
+    if ((rc = upload_run(c, c->d.Dk, Dk))) return rc;
+  }
+  if ((rc = upload_run(c, c->d.LIFTr, re.LIFT))) return rc;
+  if ((rc = upload_run(c, c->d.Vqr, re.Vq))) return rc;
+  if ((rc = upload_run(c, c->d.Pqr, re.Pq))) return rc;
   const std::vector<double> Vq64T = transpose(re.Vq, Nq, Np), Pq64T = transpose(re.Pq, Np, Nq);
   if ((rc = upload(c, c->d.Vq64T, Vq64T.data(), Vq64T.size() * 8))) return rc;
   if ((rc = upload(c, c->d.Pq64T, Pq64T.data(), Pq64T.size() * 8))) return rc;
@@ -391,8 +417,25 @@ int ewdg_bind_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_receivers,
   if ((rc = upload(c, c->d.conn, m.conn.data(), m.conn.size() * 4))) return rc;
   std::vector<int32_t> nbn(re.nbrnode.begin(), re.nbrnode.end()), fm(re.Fmask.begin(), re.Fmask.end());
   if ((rc = upload(c, c->d.nbrnode, nbn.data(), nbn.size() * 4))) return rc;
+  {
+    // face-local index on the neighbour's face g of the node matching own
+    // face point j: the inverse of Fmask on face g applied to nbrnode
+    std::vector<int32_t> nbf(nbn.size(), -1);
+    for (int f = 0; f < 4; ++f)
+      for (int g = 0; g < 4; ++g)
+        for (int p = 0; p < 6; ++p)
+          for (int j = 0; j < Nfp; ++j) {
+            const size_t at = ((static_cast<size_t>(f) * 4 + g) * 6 + p) * Nfp + j;
+            for (int jj = 0; jj < Nfp; ++jj)
+              if (re.Fmask[g * Nfp + jj] == re.nbrnode[at]) nbf[at] = jj;
+            if (nbf[at] < 0) return c->fail(EWDG_EINVAL, "face node table is inconsistent");
+          }
+    if ((rc = upload(c, c->d.nbrface, nbf.data(), nbf.size() * 4))) return rc;
+  }
   if ((rc = upload(c, c->d.fmask, fm.data(), fm.size() * 4))) return rc;
   c->bound = true;
+  c->adj_bound = false;
+  c->fwd_done = false;
   c->has_material = false;
   c->has_source = false;
   c->nr = 0;
@@ -428,6 +471,7 @@ int ewdg_set_material(ewdg_ctx* c, const double* rho, const double* lam, const d
   c->cur = 0;
   c->t = 0.0;
   c->has_material = true;
+  c->fwd_done = false;
   if (c->has_source) {
     if ((rc = c->hip(launch_source_vector(c->d, c->src_elem, c->stream), "source vector"))) return rc;
   }
@@ -490,6 +534,7 @@ int ewdg_set_source(ewdg_ctx* c, const double xs[3], const double dir[3], double
   int rc;
   if ((rc = upload(c, c->d.srcb, row.data(), row.size() * 8))) return rc;
   c->has_source = true;
+  c->fwd_done = false;
   c->src_elem = e;
   for (int i = 0; i < 3; ++i) c->src_dir[i] = dir[i];
   c->src_amp = amp;
@@ -505,6 +550,7 @@ int ewdg_set_source(ewdg_ctx* c, const double xs[3], const double dir[3], double
 int ewdg_clear_source(ewdg_ctx* c) {
   if (!c) return EWDG_EINVAL;
   c->has_source = false;
+  c->fwd_done = false;
   c->src_elem = -1;
   return EWDG_OK;
 }
@@ -530,6 +576,7 @@ int ewdg_set_receivers(ewdg_ctx* c, int nr, const double* xr) {
   }
   c->nr = nr;
   c->rec_count = 0;
+  c->fwd_done = false;
   return EWDG_OK;
 }
 
@@ -708,6 +755,225 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
     }
   }
   return EWDG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ adjoint
+namespace {
+
+// Layout of the adjoint workspace; with base == nullptr only the size.
+size_t adj_layout(const ewdg_ctx* c, int max_steps, int every, int max_rec, char* base, AdjDev* ad) {
+  const size_t K = static_cast<size_t>(c->mesh.K), Np = c->re.Np, Nfp = c->re.Nfp, ts = c->tsz();
+  const size_t nck = (static_cast<size_t>(max_steps) + every - 1) / every;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  AdjDev a;
+  a.ytil = take(3 * Np * K * ts);
+  a.fown = take(32 * Nfp * K * ts);
+  a.fnbr = take(32 * Nfp * K * ts);
+  a.qbar = take(9 * Np * K * ts);
+  a.rbar = take(9 * Np * K * ts);
+  a.rhs = take(9 * Np * K * ts);
+  a.res = take(9 * Np * K * ts);
+  a.g = reinterpret_cast<double*>(take(3 * K * 8));
+  a.resid = reinterpret_cast<double*>(take(static_cast<size_t>(max_steps) * (max_rec > 0 ? max_rec : 1) * 3 * 8));
+  a.ck_q = take(nck * 9 * Np * K * ts);
+  a.ck_s = take(nck * 6 * Np * K * ts);
+  a.seg_q = take(static_cast<size_t>(every) * 9 * Np * K * ts);
+  a.seg_s = take(static_cast<size_t>(every) * 6 * Np * K * ts);
+  a.st_q = take(4 * 9 * Np * K * ts);
+  a.st_s = take(4 * 6 * Np * K * ts);
+  if (ad) *ad = a;
+  return off;
+}
+
+// Snapshot slot i of a [n][K][m][Np] array.
+void* slot(void* base, const ewdg_ctx* c, int m, size_t i) {
+  return static_cast<char*>(base) + i * m * c->re.Np * static_cast<size_t>(c->mesh.K) * c->tsz();
+}
+
+int copy_dev(ewdg_ctx* c, void* dst, const void* src, int m) {
+  const size_t bytes = static_cast<size_t>(m) * c->re.Np * c->mesh.K * c->tsz();
+  return c->hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "snapshot copy");
+}
+
+// One LSRK stage on caller buffers (the context state is untouched).
+int stage_on(ewdg_ctx* c, int i, double dt, double tn, const void* qin, const void* sin, void* qout, void* sout) {
+  const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, tn + kRkC[i] * dt);
+  return c->hip(launch_stage(c->d, 1, qin, sin, qout, sout, c->ad.res, sc, c->stream), "recompute stage");
+}
+
+int need_adj(ewdg_ctx* c) {
+  if (int rc = need(c, true, true, true)) return c ? c->fail(rc, "adjoint needs a mesh, workspace and material") : rc;
+  if (!c->adj_bound) return c->fail(EWDG_ESTATE, "no adjoint workspace bound");
+  return EWDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ewdg_adjoint_workspace_bytes(const ewdg_ctx* c, int max_steps, int checkpoint_every, size_t* bytes) {
+  if (int rc = need(c, true, true, false)) return rc;
+  if (!bytes || max_steps < 1 || checkpoint_every < 1) return EWDG_EINVAL;
+  *bytes = adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr);
+  return EWDG_OK;
+}
+
+int ewdg_bind_adjoint_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_steps, int checkpoint_every) {
+  if (int rc = need(c, true, true, false)) return c ? c->fail(rc, "bind the forward workspace first") : rc;
+  if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
+    return c->fail(EWDG_EINVAL, "adjoint workspace must be a non-null 256-byte aligned device pointer");
+  if (max_steps < 1 || checkpoint_every < 1) return c->fail(EWDG_EINVAL, "max_steps and checkpoint_every must be >= 1");
+  if (bytes < adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr))
+    return c->fail(EWDG_ENOMEM, "adjoint workspace smaller than ewdg_adjoint_workspace_bytes");
+  adj_layout(c, max_steps, checkpoint_every, c->max_rec, static_cast<char*>(ptr), &c->ad);
+  // the recomputation register is scaled by a_1 = 0 at every step start, so
+  // it only has to hold finite values
+  if (int rc = c->hip(hipMemsetAsync(c->ad.res, 0, 9 * static_cast<size_t>(c->re.Np) * c->mesh.K * c->tsz(),
+                                     c->stream), "memset"))
+    return rc;
+  c->adj_bound = true;
+  c->adj_max_steps = max_steps;
+  c->adj_every = checkpoint_every;
+  c->adj_rec = c->max_rec;
+  c->fwd_done = false;
+  return c->hip(hipStreamSynchronize(c->stream), "adjoint bind sync");
+}
+
+int ewdg_rhs_adjoint(ewdg_ctx* c, double t, const void* q, const void* y, void* LTy, double* g) {
+  if (int rc = need_adj(c)) return rc;
+  if (!y || !LTy || (g && !q)) return c->fail(EWDG_EINVAL, "rhs_adjoint needs y, LTy, and q when g is requested");
+  const size_t n = 9 * static_cast<size_t>(c->re.Np) * c->mesh.K;
+  int rc;
+  if ((rc = c->hip(hipMemsetAsync(LTy, 0, n * c->tsz(), c->stream), "memset"))) return rc;
+  const void* s = nullptr;
+  if (q) {
+    s = c->ad.st_s;
+    if ((rc = c->hip(launch_sigma(c->d, q, c->ad.st_s, c->stream), "sigma"))) return rc;
+    const StageCoef sc = coef(c, 0.0, 0.0, 0.0, t);
+    if ((rc = c->hip(launch_stage(c->d, 0, q, s, nullptr, nullptr, c->ad.rhs, sc, c->stream), "rhs"))) return rc;
+  }
+  if (g) {
+    if ((rc = c->hip(hipMemsetAsync(g, 0, 3 * static_cast<size_t>(c->mesh.K) * 8, c->stream), "memset"))) return rc;
+  }
+  return c->hip(launch_adjoint(c->d, c->ad, y, q, s, c->ad.rhs, LTy, g, 1.0, c->stream), "adjoint");
+}
+
+int ewdg_forward_misfit(ewdg_ctx* c, double dt, int nsteps, const double* data, double* J) {
+  if (int rc = need_adj(c)) return rc;
+  if (!(dt > 0.0) || nsteps < 1 || !J || (c->nr > 0 && !data)) return c->fail(EWDG_EINVAL, "bad forward_misfit arguments");
+  if (nsteps > c->adj_max_steps) return c->fail(EWDG_ENOMEM, "more steps than the adjoint workspace holds");
+  if (c->nr > c->adj_rec) return c->fail(EWDG_ENOMEM, "more receivers than the adjoint workspace holds");
+  if (c->nr > 0 && nsteps > c->max_steps) return c->fail(EWDG_ENOMEM, "receiver record capacity exceeded");
+  c->fwd_done = false;
+  c->rec_count = 0;
+  c->step_t.assign(nsteps, 0.0);
+  const int C = c->adj_every;
+  int rc;
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % C == 0) {
+      const size_t k = n / C;
+      if ((rc = copy_dev(c, slot(c->ad.ck_q, c, 9, k), c->d.q[c->cur], 9))) return rc;
+      if ((rc = copy_dev(c, slot(c->ad.ck_s, c, 6, k), c->d.s[c->cur], 6))) return rc;
+    }
+    c->step_t[n] = c->t;
+    if ((rc = ewdg_step(c, dt, 1))) return rc;
+  }
+  double acc = 0.0;
+  if (c->nr > 0) {
+    const size_t m = static_cast<size_t>(nsteps) * c->nr * 3;
+    std::vector<double> tr(m), r(m);
+    int ns = 0;
+    if ((rc = ewdg_receivers(c, tr.data(), &ns))) return rc;
+    for (size_t i = 0; i < m; ++i) {
+      r[i] = tr[i] - data[i];
+      acc += r[i] * r[i];
+    }
+    if ((rc = c->hip(hipMemcpy(c->ad.resid, r.data(), m * 8, hipMemcpyHostToDevice), "residual upload"))) return rc;
+  }
+  if ((rc = c->hip(hipStreamSynchronize(c->stream), "forward sync"))) return rc;
+  *J = 0.5 * dt * acc;
+  c->fwd_steps = nsteps;
+  c->fwd_dt = dt;
+  c->fwd_done = true;
+  return EWDG_OK;
+}
+
+int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
+  if (int rc = need_adj(c)) return rc;
+  if (!g) return c->fail(EWDG_EINVAL, "adjoint_gradient needs g");
+  if (!c->fwd_done) return c->fail(EWDG_ESTATE, "no recorded forward run (ewdg_forward_misfit)");
+  const int64_t K = c->mesh.K;
+  const size_t n9 = 9 * static_cast<size_t>(c->re.Np) * K;
+  const int C = c->adj_every, NS = c->fwd_steps;
+  const double dt = c->fwd_dt;
+  const AdjDev& a = c->ad;
+  int rc;
+  if ((rc = c->hip(hipMemsetAsync(a.qbar, 0, n9 * c->tsz(), c->stream), "memset"))) return rc;
+  if ((rc = c->hip(hipMemsetAsync(a.rbar, 0, n9 * c->tsz(), c->stream), "memset"))) return rc;
+  if ((rc = c->hip(hipMemsetAsync(a.g, 0, 3 * static_cast<size_t>(K) * 8, c->stream), "memset"))) return rc;
+  const int nseg = (NS + C - 1) / C;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * C, len = std::min(C, NS - s0);
+    // step-start states of the segment, recomputed from its checkpoint
+    if ((rc = copy_dev(c, a.seg_q, slot(a.ck_q, c, 9, seg), 9))) return rc;
+    if ((rc = copy_dev(c, a.seg_s, slot(a.ck_s, c, 6, seg), 6))) return rc;
+    for (int m = 0; m + 1 < len; ++m) {
+      const double tn = c->step_t[s0 + m];
+      const void* qi = slot(a.seg_q, c, 9, m);
+      const void* si = slot(a.seg_s, c, 6, m);
+      for (int i = 0; i < 5; ++i) {
+        void* qo = i < 4 ? slot(a.st_q, c, 9, i) : slot(a.seg_q, c, 9, m + 1);
+        void* so = i < 4 ? slot(a.st_s, c, 6, i) : slot(a.seg_s, c, 6, m + 1);
+        if ((rc = stage_on(c, i, dt, tn, qi, si, qo, so))) return rc;
+        qi = qo;
+        si = so;
+      }
+    }
+    for (int m = len - 1; m >= 0; --m) {
+      const int n = s0 + m;
+      const double tn = c->step_t[n];
+      // misfit term of the state after step n
+      if (c->nr > 0) {
+        if ((rc = c->hip(launch_adj_receivers(c->d, a.qbar, a.resid + static_cast<size_t>(n) * c->nr * 3, c->nr, dt,
+                                              c->stream), "adjoint receivers")))
+          return rc;
+      }
+      // stage inputs q_1..q_4 of step n
+      const void* qi = slot(a.seg_q, c, 9, m);
+      const void* si = slot(a.seg_s, c, 6, m);
+      for (int i = 0; i < 4; ++i) {
+        if ((rc = stage_on(c, i, dt, tn, qi, si, slot(a.st_q, c, 9, i), slot(a.st_s, c, 6, i)))) return rc;
+        qi = slot(a.st_q, c, 9, i);
+        si = slot(a.st_s, c, 6, i);
+      }
+      for (int i = 4; i >= 0; --i) {
+        const void* qin = i == 0 ? slot(a.seg_q, c, 9, m) : slot(a.st_q, c, 9, i - 1);
+        const void* sin = i == 0 ? slot(a.seg_s, c, 6, m) : slot(a.st_s, c, 6, i - 1);
+        if ((rc = c->hip(launch_axpy(c->prec, a.rbar, a.qbar, kRkB[i], static_cast<int64_t>(n9), c->stream), "axpy")))
+          return rc;
+        const StageCoef sc = coef(c, 0.0, 0.0, 0.0, tn + kRkC[i] * dt);
+        if ((rc = c->hip(launch_stage(c->d, 0, qin, sin, nullptr, nullptr, a.rhs, sc, c->stream), "rhs"))) return rc;
+        if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, qin, sin, a.rhs, a.qbar, a.g, dt, c->stream), "adjoint")))
+          return rc;
+        if ((rc = c->hip(launch_scal(c->prec, a.rbar, kRkA[i], static_cast<int64_t>(n9), c->stream), "scal")))
+          return rc;
+      }
+    }
+  }
+  if ((rc = c->hip(hipMemcpyAsync(g, a.g, 3 * static_cast<size_t>(K) * 8, hipMemcpyDefault, c->stream), "g copy")))
+    return rc;
+  if (qbar0) {
+    if ((rc = c->hip(hipMemcpyAsync(qbar0, a.qbar, n9 * c->tsz(), hipMemcpyDefault, c->stream), "qbar copy")))
+      return rc;
+  }
+  return c->hip(hipStreamSynchronize(c->stream), "adjoint sync");
 }
 
 }  // extern "C"

@@ -30,6 +30,11 @@ struct Dev {
   void* Pqpad = nullptr;             // quadrature points -> nodes (L2_Q projection)
   void* VqT = nullptr;               // [Np][Nq]
   void* PqT = nullptr;               // [Nq][Np]
+  // row-major operators for the adjoint kernels
+  void* Dk = nullptr;                // [3][Np][Np] Dr, Ds, Dt
+  void* LIFTr = nullptr;             // [Np][4 Nfp]
+  void* Vqr = nullptr;               // [Nq][Np]
+  void* Pqr = nullptr;               // [Np][Nq]
   // FP64
   double* Vq64T = nullptr;           // [Np][Nq]
   double* Pq64T = nullptr;           // [Nq][Np]
@@ -39,6 +44,7 @@ struct Dev {
   double* lam64 = nullptr;
   double* mu64 = nullptr;
   double* J64 = nullptr;             // [K]
+  double* means64 = nullptr;         // [K][3] element means of rho, lambda, mu
   double* epart = nullptr;           // [K] energy partials
   double* scal = nullptr;            // [64] small scalars (energy result, source basis)
   double* srcb = nullptr;            // [Np] nodal basis values at the source point
@@ -48,7 +54,8 @@ struct Dev {
   double* rec_out = nullptr;         // [max_steps][max_rec][3]
   // int32
   int32_t* conn = nullptr;           // [K][4] nbr*32 + g*6 + p
-  int32_t* nbrnode = nullptr;        // [4][4][6][Nfp]
+  int32_t* nbrnode = nullptr;        // [4][4][6][Nfp] neighbour volume node
+  int32_t* nbrface = nullptr;        // [4][4][6][Nfp] neighbour face-local node
   int32_t* fmask = nullptr;          // [4][Nfp]
   // scratch for setup (aliases q[1], s[1], res while no state exists)
   void* scratch = nullptr;

@@ -663,6 +663,9 @@ __global__ __launch_bounds__(256) void k_material(Dev d, int64_t e_begin) {
     T* Z = static_cast<T*>(d.Z) + e * 2;
     Z[0] = static_cast<T>(sqrt(r * (l + 2.0 * m)));
     Z[1] = static_cast<T>(sqrt(r * m));
+    d.means64[e * 3 + 0] = r;
+    d.means64[e * 3 + 1] = l;
+    d.means64[e * 3 + 2] = m;
   }
 }
 

@@ -55,6 +55,11 @@ SIGNATURES = {
     "ewdg_energy": [_c_p, _P_d],
     "ewdg_batch_table_bytes": [_c_i, ctypes.POINTER(_c_sz)],
     "ewdg_step_batch": [ctypes.POINTER(_c_p), _c_i, ctypes.POINTER(_c_d), _c_i, _c_p, _c_sz, _c_p],
+    "ewdg_adjoint_workspace_bytes": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
+    "ewdg_bind_adjoint_workspace": [_c_p, _c_p, _c_sz, _c_i, _c_i],
+    "ewdg_rhs_adjoint": [_c_p, _c_d, _c_p, _c_p, _c_p, _c_p],
+    "ewdg_forward_misfit": [_c_p, _c_d, _c_i, _c_p, _P_d],
+    "ewdg_adjoint_gradient": [_c_p, _c_p, _c_p],
     "ewdg_last_error": [_c_p],
 }
 _RESTYPE = {"ewdg_last_error": ctypes.c_char_p}
@@ -111,6 +116,7 @@ class Context:
         self.N = int(N)
         self.precision = int(precision)
         self._ws = None
+        self._adj_ws = None
         h = _c_p()
         rc = self.lib.ewdg_create(self.N, self.precision, _c_p(stream), ctypes.byref(h))
         if rc != EWDG_OK:
@@ -145,6 +151,7 @@ class Context:
             self.lib.ewdg_destroy(self.h)
             self.h = None
         self._ws = None
+        self._adj_ws = None
 
     def __del__(self):
         try:
@@ -299,6 +306,57 @@ class Context:
         e = _c_d()
         self._check(self.lib.ewdg_energy(self.h, ctypes.byref(e)), "energy")
         return e.value
+
+    # -------------------------------------------------------------- adjoint
+    def adjoint_workspace_bytes(self, max_steps, checkpoint_every=50):
+        b = _c_sz()
+        self._check(self.lib.ewdg_adjoint_workspace_bytes(self.h, int(max_steps), int(checkpoint_every),
+                                                          ctypes.byref(b)), "adjoint_workspace_bytes")
+        return b.value
+
+    def bind_adjoint_workspace(self, max_steps, checkpoint_every=50, buffer=None):
+        torch = _torch()
+        nbytes = self.adjoint_workspace_bytes(max_steps, checkpoint_every)
+        if buffer is None:
+            buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._check(self.lib.ewdg_bind_adjoint_workspace(self.h, _ptr(buffer), buffer.numel() * buffer.element_size(),
+                                                         int(max_steps), int(checkpoint_every)),
+                    "bind_adjoint_workspace")
+        self._adj_ws = buffer
+        return buffer
+
+    def rhs_adjoint(self, t, y, q=None, grad=False):
+        """L^T y, and with grad=True also y . d(L q + f)/d theta ([K][3] FP64)."""
+        torch = _torch()
+        y = y.to(device="cuda", dtype=self.torch_dtype).contiguous()
+        self._shape(y, 9 * self.Np)
+        if q is not None:
+            q = q.to(device="cuda", dtype=self.torch_dtype).contiguous()
+            self._shape(q, 9 * self.Np)
+        out = torch.empty_like(y)
+        g = torch.empty((self.K, 3), dtype=torch.float64, device="cuda") if grad else None
+        self._check(self.lib.ewdg_rhs_adjoint(self.h, float(t), _c_p(None) if q is None else _ptr(q), _ptr(y),
+                                              _ptr(out), _c_p(None) if g is None else _ptr(g)), "rhs_adjoint")
+        return (out, g) if grad else out
+
+    def forward_misfit(self, dt, nsteps, data):
+        """Run nsteps from the stored state, checkpointing; J for data[nsteps][nr][3]."""
+        d = _host(data, np.float64)
+        if d.size != int(nsteps) * getattr(self, "nr", 0) * 3:
+            raise EwdgError(EWDG_EINVAL, "data must be [nsteps][nr][3]")
+        J = _c_d()
+        self._check(self.lib.ewdg_forward_misfit(self.h, float(dt), int(nsteps), _ptr(d) if d.size else _c_p(None),
+                                                 ctypes.byref(J)), "forward_misfit")
+        return J.value
+
+    def adjoint_gradient(self, want_qbar0=False):
+        """(g [K][3] FP64 device tensor, dJ/dq0 [K][9][Np] or None)."""
+        torch = _torch()
+        g = torch.empty((self.K, 3), dtype=torch.float64, device="cuda")
+        qb = torch.empty((self.K, 9, self.Np), dtype=self.torch_dtype, device="cuda") if want_qbar0 else None
+        self._check(self.lib.ewdg_adjoint_gradient(self.h, _ptr(g), _c_p(None) if qb is None else _ptr(qb)),
+                    "adjoint_gradient")
+        return g, qb
 
 
 def batch_table_bytes(n):
