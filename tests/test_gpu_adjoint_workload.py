@@ -1,0 +1,86 @@
+"""Misfit gradient at the inversion workload's full size.
+
+12^3 hexahedra x 6 = 10,368 tetrahedra, N=4, 16 receivers, 800 LSRK(5,4)
+steps at CFL 0.5 with checkpoints every 50 steps; observed traces from the
+medium with a Gaussian bump in mu, gradient at the smooth reference medium.
+The FP64 adjoint gradient is checked against central finite differences of
+the FP64 misfit on 20 random elements (one test per field, relative
+tolerance 1e-4); the FP32 gradient is compared with the FP64 one.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection, outside the per-test time limit)
+
+pytestmark = pytest.mark.gpu
+
+NSTEPS, EVERY, N, NHEX = 800, 50, 4, 12
+
+
+def _report(name, **kw):
+    print(name, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}" for k, v in kw.items()),
+          flush=True)
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+
+    import paper_1711_01175_amd as P
+    from workloads import inversion
+    from workloads.mesh import kuhn_periodic_mesh
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    EToV, VXYZ = kuhn_periodic_mesh(NHEX)
+    rec = inversion.receiver_grid()
+    S = inversion.SOURCE
+    out = {}
+    for prec in (64, 32):
+        c = P.Context(N, prec)
+        c.set_mesh(EToV, VXYZ)
+        c.bind_workspace(len(rec), NSTEPS)
+        c.bind_adjoint_workspace(NSTEPS, EVERY)
+        ref, true = inversion.media_pair(c.quadrature_points())
+        c.set_source(S["xs"], S["direction"], S["amp"], S["f0"], S["t0"])
+        c.set_receivers(rec)
+        if prec == 64:
+            c.set_material(*true)
+            dt = c.cfl_dt(0.5)
+            c.step(dt, NSTEPS)
+            data = c.receivers()
+        c.set_material(*ref)
+        J = c.forward_misfit(dt, NSTEPS, data)
+        g, _ = c.adjoint_gradient()
+        out[prec] = dict(ctx=c, J=J, g=g.cpu().numpy())
+        _report("workload", prec=prec, K=c.K, J=J, g_norm=float(np.linalg.norm(out[prec]["g"])))
+    out.update(ref=ref, dt=dt, data=data, elems=inversion.sensitive_elements(VXYZ))
+    yield out
+    for prec in (64, 32):
+        out[prec]["ctx"].close()
+
+
+@pytest.mark.parametrize("field", [0, 1, 2], ids=["rho", "lambda", "mu"])
+def test_gradient_vs_finite_differences(case, field):
+    c, g = case[64]["ctx"], case[64]["g"]
+    h = 1e-4
+    fd = np.zeros(len(case["elems"]))
+    for a, e in enumerate(case["elems"]):
+        Js = []
+        for s in (1 + h, 1 - h):
+            m = [x.copy() for x in case["ref"]]
+            m[field][e] *= s
+            c.set_material(*m)
+            Js.append(c.forward_misfit(case["dt"], NSTEPS, case["data"]))
+        fd[a] = (Js[0] - Js[1]) / (2 * h)
+    ad = g[case["elems"], field]
+    rel = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    worst = np.max(np.abs(ad - fd)) / np.max(np.abs(fd))
+    _report("fd", field=field, rel_l2=float(rel), worst_rel_to_max=float(worst),
+            max_abs_g=float(np.max(np.abs(fd))))
+    assert rel <= 1e-4 and worst <= 1e-4
+
+
+def test_fp32_gradient_vs_fp64(case):
+    g64, g32 = case[64]["g"], case[32]["g"]
+    rel = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    jrel = abs(case[32]["J"] - case[64]["J"]) / case[64]["J"]
+    _report("fp32", g_rel_l2=float(rel), J_rel=float(jrel))
+    assert rel <= 1e-3 and jrel <= 1e-4
