@@ -23,6 +23,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_stage_cube32_N4.md")
+KERNEL_SOURCES = ("kernels.hip", "kcommon.hpp", "dev.hpp")
+
+
+def kernel_source_digest():
+    """sha256 over the stage kernel's sources, to tell whether the committed
+    counter profile was taken on the kernel that runs now."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1711_01175_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(prec):
+    """HBM bytes per stage launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None if
+    the profile is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("traffic-record "):
+            k, _, v = line[len("traffic-record "):].partition("=")
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    v = vals.get(f"bytes_per_launch_fp{prec}")
+    return int(v) if v else None
 METRIC = "DG RHS GDOF/s at N=4, FP32 vs FP64 vs oracle; batched solve p50/p99 latency"
 
 
@@ -122,6 +155,63 @@ def run_serving(full=False):
     return out
 
 
+def run_adjoint(check_fp64=True):
+    """Misfit gradient on the inversion workload: 12^3 x 6 = 10,368 tets,
+    N=4, 16 receivers, 800 steps at CFL 0.5, checkpoints every 50 steps,
+    data from the Gaussian-mu model.  Times the checkpointed forward and
+    the reverse sweep in FP32 and reports the FP32 gradient's distance from
+    the FP64 one."""
+    import torch
+
+    import paper_1711_01175_amd as P
+    from workloads import inversion
+    from workloads.mesh import kuhn_periodic_mesh
+    nsteps, every, N = 800, 50, 4
+    EToV, VXYZ = kuhn_periodic_mesh(12)
+    rec = inversion.receiver_grid()
+    S = inversion.SOURCE
+    res = {}
+    data = dt = None
+    for prec in ((64, 32) if check_fp64 else (32,)):
+        stream = torch.cuda.current_stream()
+        c = P.Context(N, prec, stream=stream.cuda_stream)
+        c.set_mesh(EToV, VXYZ)
+        c.bind_workspace(len(rec), nsteps)
+        c.bind_adjoint_workspace(nsteps, every)
+        ref, true = inversion.media_pair(c.quadrature_points())
+        c.set_source(S["xs"], S["direction"], S["amp"], S["f0"], S["t0"])
+        c.set_receivers(rec)
+        if data is None:
+            c.set_material(*true)
+            dt = c.cfl_dt(0.5)
+            c.step(dt, nsteps)
+            data = c.receivers()
+        c.set_material(*ref)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = c.forward_misfit(dt, nsteps, data)
+        t1 = time.perf_counter()
+        g, _ = c.adjoint_gradient()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[prec] = dict(J=J, g=g.cpu().numpy(), fwd=t1 - t0, adj=t2 - t1, K=c.K,
+                         ws=c.workspace_bytes(len(rec), nsteps) + c.adjoint_workspace_bytes(nsteps, every))
+        c.close()
+        torch.cuda.empty_cache()
+    r = res[32]
+    out = {"workload": f"12^3 hexes x 6 = {r['K']} tets, N=4, 16 receivers, {nsteps} LSRK steps at CFL 0.5, "
+                       f"checkpoints every {every} steps, data from a Gaussian mu anomaly; FP32",
+           "forward_s": round(r["fwd"], 4), "gradient_s": round(r["adj"], 4),
+           "gradient_over_forward": round(r["adj"] / r["fwd"], 3), "J": r["J"],
+           "device_bytes": int(r["ws"])}
+    if 64 in res:
+        g64 = res[64]["g"]
+        out["fp32_vs_fp64_gradient_rel_l2"] = float(np.linalg.norm(r["g"] - g64) / np.linalg.norm(g64))
+        out["fp64_forward_s"] = round(res[64]["fwd"], 4)
+        out["fp64_gradient_s"] = round(res[64]["adj"], 4)
+    return out
+
+
 def cpu_baseline(N, n_sample, seconds):
     """Time the FP64 oracle's RHS on a smaller mesh of the same workload
     (per-element work does not depend on the mesh size)."""
@@ -165,6 +255,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-n", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full 256-request stream (several minutes)")
     ap.add_argument("--probe-copy", action="store_true",
@@ -206,7 +297,7 @@ def main():
                                f"Ricker f0=5, LSRK(5,4) at CFL 0.5",
                    "K": K, "N": args.N, "Np": Np, "dt": r32["dt"], "dof_per_stage": dof},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(32),
                      "kernel": "k_stage (fused stage)", "stage_us": round(stage_s * 1e6, 2),
                      "algorithmic_bytes_per_stage": algo},
     }
@@ -220,6 +311,8 @@ def main():
         line["energy_fp32_fp64"] = [r32["energy"], r64["energy"]]
     if not args.no_serving:
         line["serving"] = run_serving(args.serving_full)
+    if not args.no_adjoint:
+        line["adjoint"] = run_adjoint()
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(args.N, args.cpu_n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
