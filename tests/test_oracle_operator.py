@@ -209,3 +209,48 @@ def test_energy_non_increasing_over_steps():
     e0 = op.energy(c)
     seq = np.array([e0] + energies)
     assert np.all(np.diff(seq) <= 1e-14 * e0)
+
+
+def test_energy_closed_forms():
+    """Constant state in a homogeneous medium: E = 1/2 |cube| (rho |v|^2 +
+    lambda tr(e)^2 + 2 mu e:e) with |cube| = 8 (energy density of the
+    velocity-strain system).  Constant velocity, zero strain and a density
+    linear in x (integrated exactly by Q_N): E = 1/2 |v|^2 * 8 * mean(rho)."""
+    from workloads import media
+    op, EToV, VXYZ, xyz, _ = oracle_case(2, 3, medium="homogeneous", shuffle_seed=4)
+    rho, lam, mu = 1.3, 0.7, 1.1
+    from oracle.dg import Elastic
+    op = Elastic(2, VXYZ, *media.homogeneous(xyz, rho, lam, mu))
+    one = op.project_q(np.ones(op.Nq))
+    v = np.array([0.3, -1.2, 0.5])
+    e6 = np.array([0.2, -0.1, 0.4, 0.15, -0.25, 0.05])      # xx yy zz yz xz xy
+    c = np.zeros((op.K, 9, op.Np))
+    c[:, 0:3] = v[None, :, None] * one
+    c[:, 3:9] = e6[None, :, None] * one
+    ee = np.sum(e6[:3] ** 2) + 2.0 * np.sum(e6[3:] ** 2)
+    E = 0.5 * 8.0 * (rho * v @ v + lam * np.sum(e6[:3]) ** 2 + 2.0 * mu * ee)
+    assert abs(op.energy(c) - E) <= 1e-12 * E
+    r_lin = 1.0 + 0.3 * xyz[..., 0] - 0.2 * xyz[..., 2]
+    op2 = Elastic(2, VXYZ, r_lin, np.full_like(r_lin, lam), np.full_like(r_lin, mu))
+    c2 = np.zeros_like(c)
+    c2[:, 0:3] = v[None, :, None] * one
+    assert abs(op2.energy(c2) - 0.5 * 8.0 * (v @ v)) <= 1e-12 * (v @ v)
+
+
+def test_point_values_reproduce_polynomials():
+    """The projection of a global degree-N polynomial is exact in every
+    element, so its value at any point equals the polynomial's."""
+    N = 3
+    op, EToV, VXYZ, xyz, _ = oracle_case(N, 3, shuffle_seed=2)
+    rng = np.random.default_rng(12)
+    cf = rng.standard_normal((9, 4))
+
+    def poly(p):
+        x, y, z = p[..., 0], p[..., 1], p[..., 2]
+        basis = np.stack([np.ones_like(x), x * y * z, x ** 3 - y, y * z ** 2], axis=-1)
+        return basis @ cf.T
+
+    c = op.project_q(np.moveaxis(poly(xyz), -1, 1))
+    pts = rng.uniform(-0.99, 0.99, size=(25, 3))
+    got = op.eval_points(c, pts)
+    assert np.abs(got - poly(pts)).max() <= 1e-12
