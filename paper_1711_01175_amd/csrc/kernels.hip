@@ -57,8 +57,8 @@ struct Tile {
   // the velocity right-hand side and then the new strains; Y holds one face's
   // interface corrections, later the stresses at the quadrature points.
   static constexpr int X = cmax2(2 * NpK * 48, NpK * 96);
-  static constexpr int QC = NqR < 128 ? NqR : 128;  // quadrature rows per chunk (whole tiles)
-  static constexpr int Y = cmax2(NfpK * 144, QC * 48);
+  static constexpr int QC = NqR < 64 ? NqR : 64;    // quadrature rows per chunk (whole tiles)
+  static constexpr int Y = cmax2(NfpK * 144, QC * 96);
   static constexpr int GEO = E * 32;
 };
 
@@ -425,95 +425,95 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 
   // ---- sigma_h of the new state: strains at the quadrature points (matrix
   // cores), Hooke's law with the sampled lambda, mu, and the L2_Q projection
-  // back to the nodes, in chunks of at most 128 quadrature points.
-  T* Sq = sY;  // [QC][48]
-  constexpr int QC = TL::QC, NQC = (QT * 16 + QC - 1) / QC, MP = (RT * 3 + NW - 1) / NW;
-  constexpr int KQ = QC / 4;
+  // back to the nodes, in chunks of QC quadrature points with all six
+  // components per chunk.  The owner wave of node row tile R accumulates the
+  // projection of its rows for all six components, so each P_Q fragment is
+  // loaded once per tile and feeds six independent products.
+  T* Sq = sY;  // [QC][96]
+  constexpr int QC = TL::QC, NQC = (QT * 16 + QC - 1) / QC, KQ = QC / 4;
+  acc_t pq[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) pq[m] = acc_t{0, 0, 0, 0};
 #pragma unroll 1
-  for (int ch = 0; ch < 2; ++ch) {
-    acc_t pq[MP];
+  for (int qc = 0; qc < NQC; ++qc) {
+    const int q0 = qc * QC;
+    const int rows = (NqK - q0) < QC ? (NqK - q0) : QC;   // K rows of this chunk
+    // this chunk's P_Q fragments, in flight during the V_Q products
+    T pf2[KQ];
+    if (own) {
+      const T* Pr = a.Pqpad + (R * (NqK / 4) + q0 / 4) * 64 + l;
 #pragma unroll
-    for (int s = 0; s < MP; ++s) pq[s] = acc_t{0, 0, 0, 0};
-#pragma unroll 1
-    for (int qc = 0; qc < NQC; ++qc) {
-      const int q0 = qc * QC;
-      const int rows = (NqK - q0) < QC ? (NqK - q0) : QC;   // K rows of this chunk
-#pragma unroll 1
-      for (int Rq = q0 / 16 + w; Rq < QT && Rq * 16 < q0 + QC; Rq += NW) {
-        T vf[KD];
-        const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
-#pragma unroll
-        for (int kk = 0; kk < KD; ++kk) vf[kk] = Vr[kk * 64];
-        const int ge = e0 + lr;
-        // unconditional loads from clamped (valid) indices, masked after
-        const int gc = ge < Ke ? ge : Ke - 1;
-        T lam[4], mu2[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int q = Rq * 16 + M::row(lg, r);
-          const int qc = q < Nq ? q : Nq - 1;
-          lam[r] = a.lm[gc * 2 * Nq + qc];
-          mu2[r] = T(2) * a.lm[gc * 2 * Nq + Nq + qc];
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const bool ok = Rq * 16 + M::row(lg, r) < Nq && ge < Ke;
-          lam[r] = ok ? lam[r] : T(0);
-          mu2[r] = ok ? mu2[r] : T(0);
-        }
-        acc_t ac[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) ac[m] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < KD; ++kk) {
-          const int row = (4 * kk + lg) * 96 + ch * 48 + lr;
-#pragma unroll
-          for (int m = 0; m < 3; ++m) ac[m] = M::mma(vf[kk], Se[row + m * 16], ac[m]);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int q = Rq * 16 + M::row(lg, r);
-          if (q >= NqK) continue;
-          const T ltr = (ch == 0) ? lam[r] * (ac[0][r] + ac[1][r] + ac[2][r]) : T(0);
-          T* o = &Sq[(q - q0) * 48 + lr];
-          o[0] = mu2[r] * ac[0][r] + ltr;
-          o[16] = mu2[r] * ac[1][r] + ltr;
-          o[32] = mu2[r] * ac[2][r] + ltr;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < MP; ++s) {
-        const int p = w + s * NW;
-        if (p >= RT * 3) continue;
-        const int Ro = p / 3, m = p % 3;
-        __builtin_amdgcn_sched_barrier(0);   // keep each pair's fragment loads with its products
-        const T* Pr = a.Pqpad + (Ro * (NqK / 4) + q0 / 4) * 64 + l;
-        // fragments in groups of 8 k-steps: loads of a group issue together
-#pragma unroll
-        for (int k0 = 0; k0 < KQ; k0 += 8) {
-          T pf2[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) pf2[u] = (k0 + u < KQ && 4 * (k0 + u) < rows) ? Pr[(k0 + u) * 64] : T(0);
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (k0 + u < KQ && 4 * (k0 + u) < rows)
-              pq[s] = M::mma(pf2[u], Sq[(4 * (k0 + u) + lg) * 48 + m * 16 + lr], pq[s]);
-        }
-      }
-      __syncthreads();
+      for (int u = 0; u < KQ; ++u) pf2[u] = (4 * u < rows) ? Pr[u * 64] : T(0);
     }
-    const int ge = e0 + lr;
+#pragma unroll 1
+    for (int Rq = q0 / 16 + w; Rq < QT && Rq * 16 < q0 + QC; Rq += NW) {
+      T vf[KD];
+      const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
 #pragma unroll
-    for (int s = 0; s < MP; ++s) {
-      const int p = w + s * NW;
-      if (p >= RT * 3 || ge >= Ke) continue;
-      const int Ro = p / 3, m = p % 3;
+      for (int kk = 0; kk < KD; ++kk) vf[kk] = Vr[kk * 64];
+      const int ge = e0 + lr;
+      // unconditional loads from clamped (valid) indices, masked after
+      const int gc = ge < Ke ? ge : Ke - 1;
+      T lam[4], mu2[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = Ro * 16 + M::row(lg, r);
-        if (i < Np) a.sout[ge * 6 * Np + (3 * ch + m) * Np + i] = pq[s][r];
+        const int q = Rq * 16 + M::row(lg, r);
+        const int qq = q < Nq ? q : Nq - 1;
+        lam[r] = a.lm[gc * 2 * Nq + qq];
+        mu2[r] = T(2) * a.lm[gc * 2 * Nq + Nq + qq];
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool ok = Rq * 16 + M::row(lg, r) < Nq && ge < Ke;
+        lam[r] = ok ? lam[r] : T(0);
+        mu2[r] = ok ? mu2[r] : T(0);
+      }
+      acc_t ac[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) ac[m] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) {
+        const int row = (4 * kk + lg) * 96 + lr;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) ac[m] = M::mma(vf[kk], Se[row + m * 16], ac[m]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = Rq * 16 + M::row(lg, r);
+        if (q >= NqK) continue;
+        const T ltr = lam[r] * (ac[0][r] + ac[1][r] + ac[2][r]);
+        T* o = &Sq[(q - q0) * 96 + lr];
+        o[0] = mu2[r] * ac[0][r] + ltr;
+        o[16] = mu2[r] * ac[1][r] + ltr;
+        o[32] = mu2[r] * ac[2][r] + ltr;
+        o[48] = mu2[r] * ac[3][r];
+        o[64] = mu2[r] * ac[4][r];
+        o[80] = mu2[r] * ac[5][r];
+      }
+    }
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int u = 0; u < KQ; ++u) {
+        if (4 * u < rows) {
+          const int row = (4 * u + lg) * 96 + lr;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) pq[m] = M::mma(pf2[u], Sq[row + m * 16], pq[m]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (own) {
+    const int ge = e0 + lr;
+    if (ge < Ke) {
+#pragma unroll
+      for (int m = 0; m < 6; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = R * 16 + M::row(lg, r);
+          if (i < Np) a.sout[ge * 6 * Np + m * Np + i] = pq[m][r];
+        }
     }
   }
 }
