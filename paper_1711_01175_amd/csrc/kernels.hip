@@ -7,8 +7,26 @@
 #include "dev.hpp"
 #include "kcommon.hpp"
 
-namespace ewdg {
+#ifndef EWDG_SV
+#define EWDG_SV 48
+#endif
+#ifndef EWDG_SE
+#define EWDG_SE 97
+#endif
+#ifndef EWDG_SF
+#define EWDG_SF 144
+#endif
+#ifndef EWDG_SQ
+#define EWDG_SQ 96
+#endif
+#ifndef EWDG_QC
+#define EWDG_QC 64
+#endif
+#ifndef EWDG_OCC32
+#define EWDG_OCC32 4
+#endif
 
+namespace ewdg {
 
 // ---------------------------------------------------------------- MFMA tiles
 // 16x16x4 matrix-core tiles: C[16x16] += A[16x4] B[4x16].  Lane l supplies
@@ -56,9 +74,12 @@ struct Tile {
   // LDS regions (in values): X holds v and the contravariant stresses, later
   // the velocity right-hand side and then the new strains; Y holds one face's
   // interface corrections, later the stresses at the quadrature points.
-  static constexpr int X = cmax2(2 * NpK * 48, NpK * 96);
-  static constexpr int QC = NqR < 64 ? NqR : 64;    // quadrature rows per chunk (whole tiles)
-  static constexpr int Y = cmax2(NfpK * 144, QC * 96);
+  // LDS row strides (values) of the B-operand buffers: 3, 6, 9 and 6 fields
+  // of 16 element columns, padded against bank conflicts
+  static constexpr int SV = EWDG_SV, SE = EWDG_SE, SF = EWDG_SF, SQ = EWDG_SQ;
+  static constexpr int X = cmax2(2 * NpK * SV, NpK * SE);
+  static constexpr int QC = NqR < EWDG_QC ? NqR : EWDG_QC;   // quadrature rows per chunk (whole tiles)
+  static constexpr int Y = cmax2(cmax2(NfpK * SF, QC * SQ), NpK * SV);
   static constexpr int GEO = E * 32;
 };
 
@@ -140,6 +161,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   constexpr int Np = TL::Np, Nfp = TL::Nfp, Nq = TL::Nq, E = TL::E;
   constexpr int NpK = TL::NpK, NqK = TL::NqK, NfpK = TL::NfpK;
   constexpr int RT = TL::RT, QT = TL::QT, NW = TL::NW, NT = TL::NT;
+  constexpr int SV = TL::SV, SE = TL::SE, SF = TL::SF, SQ = TL::SQ;
   constexpr int KD = NpK / 4, KF = NfpK / 4;       // k-steps of the node / face contractions
   constexpr int FPT = (Nfp * E + NT - 1) / NT;      // face points per thread and face
   __shared__ T sX[TL::X];
@@ -192,17 +214,17 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     }
     sgeo[e * 32 + m] = v;
   }
-  T* Sv = sX;                // [NpK][48]  v_c of element e at column c*16+e
-  T* SG = sX + NpK * 48;     // [NpK][48]  G^k_c for the current direction k
+  T* Sv = sX;                // [NpK][SV]  v_c of element e at column c*16+e
+  T* SG = sX + NpK * SV;     // [NpK][SV]  G^k_c for the current direction k
   for (int x = tid; x < E * 3 * Np; x += NT) {
     const int e = x / (3 * Np), rem = x % (3 * Np), c = rem / Np, j = rem % Np;
     const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
     const T v = a.qin[ge * 9 * Np + c * Np + j];
-    Sv[j * 48 + c * 16 + e] = (e0 + e < Ke) ? v : T(0);
+    Sv[j * SV + c * 16 + e] = (e0 + e < Ke) ? v : T(0);
   }
-  for (int x = tid; x < (NpK - Np) * 48; x += NT) {
-    Sv[Np * 48 + x] = T(0);
-    SG[Np * 48 + x] = T(0);
+  for (int x = tid; x < (NpK - Np) * SV; x += NT) {
+    Sv[Np * SV + x] = T(0);
+    SG[Np * SV + x] = T(0);
   }
   constexpr int NPT = (E * Np + NT - 1) / NT;
   FacePt<T> pf[FPT];
@@ -235,9 +257,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         for (int m = 0; m < 6; ++m) sg[m] = a.sin[ge * 6 * Np + m * Np + j];
         const T* g = &sgeo[e * 32 + k * 3];
         // rows of sigma in Voigt order xx,yy,zz,yz,xz,xy
-        SG[j * 48 + 0 * 16 + e] = g[0] * sg[0] + g[1] * sg[5] + g[2] * sg[4];
-        SG[j * 48 + 1 * 16 + e] = g[0] * sg[5] + g[1] * sg[1] + g[2] * sg[3];
-        SG[j * 48 + 2 * 16 + e] = g[0] * sg[4] + g[1] * sg[3] + g[2] * sg[2];
+        SG[j * SV + 0 * 16 + e] = g[0] * sg[0] + g[1] * sg[5] + g[2] * sg[4];
+        SG[j * SV + 1 * 16 + e] = g[0] * sg[5] + g[1] * sg[1] + g[2] * sg[3];
+        SG[j * SV + 2 * 16 + e] = g[0] * sg[4] + g[1] * sg[3] + g[2] * sg[2];
       }
     }
     __syncthreads();
@@ -247,7 +269,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       for (int c = 0; c < 3; ++c) gv[c] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < KD; ++kk) {
-        const int row = (4 * kk + lg) * 48 + lr;
+        const int row = (4 * kk + lg) * SV + lr;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           rhs[c] = M::mma(af[kk], SG[row + c * 16], rhs[c]);
@@ -270,8 +292,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   }
 
   // ---- interface corrections, one face at a time, lifted on the matrix cores
-  T* Sf = sY;  // [NfpK][144]
-  for (int x = tid; x < (NfpK - Nfp) * 144; x += NT) Sf[Nfp * 144 + x] = T(0);
+  T* Sf = sY;  // [NfpK][SF]
+  for (int x = tid; x < (NfpK - Nfp) * SF; x += NT) Sf[Nfp * SF + x] = T(0);
 #pragma unroll 1
   for (int f = 0; f < 4; ++f) {
     T lf[KF];
@@ -285,7 +307,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const int x = tid + p * NT;
       if (x >= Nfp * E) continue;
       const int e = x / Nfp, j = x % Nfp;
-      T* fl = &Sf[j * 144 + e];
+      T* fl = &Sf[j * SF + e];
       if (e0 + e >= Ke) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) fl[c * 16] = T(0);
@@ -297,7 +319,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const T fs = gg[9 + f * 4 + 3];
       T vm[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) vm[c] = Sv[il * 48 + c * 16 + e];
+      for (int c = 0; c < 3; ++c) vm[c] = Sv[il * SV + c * 16 + e];
       const T* sm = pf[p].sm;
       const T* sp = pf[p].sp;
       const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2], sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
@@ -321,7 +343,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     if (own) {
 #pragma unroll
       for (int kk = 0; kk < KF; ++kk) {
-        const int row = (4 * kk + lg) * 144 + lr;
+        const int row = (4 * kk + lg) * SF + lr;
 #pragma unroll
         for (int c = 0; c < 9; ++c) rhs[c] = M::mma(lf[kk], Sf[row + c * 16], rhs[c]);
       }
@@ -329,94 +351,72 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     __syncthreads();
   }
 
-  // ---- strain rows: update in registers, new strains to LDS for sigma_h;
-  // the velocity rows go to LDS for the per-element mass inverse.
-  T* Srv = sY;  // [NpK][48] (the face buffer is free after the lift)
-  T* Se = sX;   // [NpK][96]
+  // ---- right-hand side to LDS: velocity rows [NpK][SV] for the mass
+  // inverse, strain rows [NpK][SE] (overwritten in place by the new strains)
+  T* Srv = sY;  // (the face buffer is free after the lift)
+  T* Se = sX;
   if (own) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 4; ++r) {
+      const int i = R * 16 + M::row(lg, r);
+      if (i < NpK) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = R * 16 + M::row(lg, r);
-        if (i < NpK) Srv[i * 48 + c * 16 + lr] = rhs[c][r];
+        for (int c = 0; c < 3; ++c) Srv[i * SV + c * 16 + lr] = rhs[c][r];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) Se[i * SE + m * 16 + lr] = rhs[3 + m][r];
       }
-    const int ge = e0 + lr;
-    // all loads first, then the stores (res and q may not be proven disjoint
-    // by the compiler, which would otherwise serialise every round trip)
-    T rv[6][4], qv[6][4];
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = R * 16 + M::row(lg, r);
-        rv[m][r] = T(0);
-        qv[m][r] = T(0);
-        if (MODE == 1 && i < Np && ge < Ke) {
-          const int idx = ge * 9 * Np + (3 + m) * Np + i;
-          rv[m][r] = a.out[idx];
-          qv[m][r] = a.qin[idx];
-        }
-      }
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = R * 16 + M::row(lg, r);
-        if (i >= NpK) continue;
-        T qn = T(0);
-        if (i < Np && ge < Ke) {
-          const int idx = ge * 9 * Np + (3 + m) * Np + i;
-          if (MODE == 0) {
-            a.out[idx] = rhs[3 + m][r];
-          } else {
-            const T rr = a.a * rv[m][r] + a.dt * rhs[3 + m][r];
-            qn = qv[m][r] + a.b * rr;
-            a.out[idx] = rr;
-            a.qout[idx] = qn;
-          }
-        }
-        Se[i * 96 + m * 16 + lr] = qn;
-      }
+    }
   }
   __syncthreads();
 
-  // ---- density-weighted mass inverse on the velocity rows (per element)
-  for (int x = tid; x < E * Np; x += NT) {
+  // ---- per (element, node): density-weighted mass inverse on the velocity
+  // rows, point source, LSRK update of all nine fields with coalesced
+  // accesses; the new strains replace their right-hand side in LDS.
+  constexpr int NPU = (E * Np + NT - 1) / NT;
+#pragma unroll
+  for (int p = 0; p < NPU; ++p) {
+    const int x = tid + p * NT;
+    if (x >= E * Np) break;
     const int e = x / Np, i = x % Np;
     const int ge = e0 + e;
     if (ge >= Ke) continue;
-    const T* Wm = a.W + ge * Np * Np + i;
-    T rv[3], qv[3];
+    const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
+    const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
+    T rv[9], qv[9];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      rv[c] = (MODE == 1) ? a.out[ge * 9 * Np + c * Np + i] : T(0);
-      qv[c] = (MODE == 1) ? a.qin[ge * 9 * Np + c * Np + i] : T(0);
+    for (int c = 0; c < 9; ++c) {
+      rv[c] = (MODE == 1) ? a.out[base + c * Np] : T(0);
+      qv[c] = (MODE == 1) ? a.qin[base + c * Np] : T(0);
     }
-    T o0 = 0, o1 = 0, o2 = 0;
+    T o[9];
+    o[0] = 0;
+    o[1] = 0;
+    o[2] = 0;
 #pragma unroll 8
     for (int j = 0; j < Np; ++j) {
-      const T wv = Wm[j * Np];
-      o0 += wv * Srv[j * 48 + e];
-      o1 += wv * Srv[j * 48 + 16 + e];
-      o2 += wv * Srv[j * 48 + 32 + e];
+      const T w = Wm[j * Np];
+      o[0] += w * Srv[j * SV + e];
+      o[1] += w * Srv[j * SV + 16 + e];
+      o[2] += w * Srv[j * SV + 32 + e];
     }
     if (ge == a.src_elem) {
       const T sv = a.srcval * a.svec[i];
-      o0 += sv * a.dir0;
-      o1 += sv * a.dir1;
-      o2 += sv * a.dir2;
+      o[0] += sv * a.dir0;
+      o[1] += sv * a.dir1;
+      o[2] += sv * a.dir2;
     }
-    const T o[3] = {o0, o1, o2};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int idx = ge * 9 * Np + c * Np + i;
+    for (int m = 0; m < 6; ++m) o[3 + m] = Se[i * SE + m * 16 + e];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
       if (MODE == 0) {
-        a.out[idx] = o[c];
+        a.out[base + c * Np] = o[c];
       } else {
         const T rr = a.a * rv[c] + a.dt * o[c];
-        a.out[idx] = rr;
-        a.qout[idx] = qv[c] + a.b * rr;
+        const T qn = qv[c] + a.b * rr;
+        a.out[base + c * Np] = rr;
+        a.qout[base + c * Np] = qn;
+        if (c >= 3) Se[i * SE + (c - 3) * 16 + e] = qn;
       }
     }
   }
@@ -429,7 +429,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // components per chunk.  The owner wave of node row tile R accumulates the
   // projection of its rows for all six components, so each P_Q fragment is
   // loaded once per tile and feeds six independent products.
-  T* Sq = sY;  // [QC][96]
+  T* Sq = sY;  // [QC][SQ]
   constexpr int QC = TL::QC, NQC = (QT * 16 + QC - 1) / QC, KQ = QC / 4;
   acc_t pq[6];
 #pragma unroll
@@ -473,7 +473,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       for (int m = 0; m < 6; ++m) ac[m] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < KD; ++kk) {
-        const int row = (4 * kk + lg) * 96 + lr;
+        const int row = (4 * kk + lg) * SE + lr;
 #pragma unroll
         for (int m = 0; m < 6; ++m) ac[m] = M::mma(vf[kk], Se[row + m * 16], ac[m]);
       }
@@ -482,7 +482,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         const int q = Rq * 16 + M::row(lg, r);
         if (q >= NqK) continue;
         const T ltr = lam[r] * (ac[0][r] + ac[1][r] + ac[2][r]);
-        T* o = &Sq[(q - q0) * 96 + lr];
+        T* o = &Sq[(q - q0) * SQ + lr];
         o[0] = mu2[r] * ac[0][r] + ltr;
         o[16] = mu2[r] * ac[1][r] + ltr;
         o[32] = mu2[r] * ac[2][r] + ltr;
@@ -496,7 +496,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
       for (int u = 0; u < KQ; ++u) {
         if (4 * u < rows) {
-          const int row = (4 * u + lg) * 96 + lr;
+          const int row = (4 * u + lg) * SQ + lr;
 #pragma unroll
           for (int m = 0; m < 6; ++m) pq[m] = M::mma(pf2[u], Sq[row + m * 16], pq[m]);
         }
@@ -504,23 +504,28 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     }
     __syncthreads();
   }
+  // new sigma_h through LDS (the strain buffer is free), stored coalesced
+  T* Ss = sX;   // [NpK][SE]
   if (own) {
-    const int ge = e0 + lr;
-    if (ge < Ke) {
 #pragma unroll
-      for (int m = 0; m < 6; ++m)
+    for (int r = 0; r < 4; ++r) {
+      const int i = R * 16 + M::row(lg, r);
+      if (i < Np) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = R * 16 + M::row(lg, r);
-          if (i < Np) a.sout[ge * 6 * Np + m * Np + i] = pq[m][r];
-        }
+        for (int m = 0; m < 6; ++m) Ss[i * SE + m * 16 + lr] = pq[m][r];
+      }
     }
+  }
+  __syncthreads();
+  for (int x = tid; x < E * 6 * Np; x += NT) {
+    const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, i = rem % Np;
+    if (e0 + e < Ke) a.sout[static_cast<int64_t>(e0 + e) * 6 * Np + rem] = Ss[i * SE + m * 16 + e];
   }
 }
 
 // One mesh: workgroups map to element tiles, XCD-contiguous.
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage(StageArgs<T> a) {
+__global__ __launch_bounds__((Tile<N>::NT), (sizeof(T) == 4 ? EWDG_OCC32 : 2)) void k_stage(StageArgs<T> a) {
   const int nblk = static_cast<int>((a.K + Tile<N>::E - 1) / Tile<N>::E);
   stage_body<T, N, MODE>(a, static_cast<int>(xcd_tile(blockIdx.x, nblk)));
 }
@@ -529,7 +534,7 @@ __global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage(StageArgs<T> a) {
 // owns workgroups [tile_start[r], tile_start[r+1]); each request's arithmetic
 // is exactly that of its own single-mesh launch.
 template <typename T, int N>
-__global__ __launch_bounds__((Tile<N>::NT), 2) void k_stage_batch(const char* __restrict__ table,
+__global__ __launch_bounds__((Tile<N>::NT), (sizeof(T) == 4 ? EWDG_OCC32 : 2)) void k_stage_batch(const char* __restrict__ table,
                                                                    int record_bytes,
                                                                    const int* __restrict__ tile_start,
                                                                    int nreq) {
