@@ -22,6 +22,9 @@
 #ifndef EWDG_QC
 #define EWDG_QC 64
 #endif
+#ifndef EWDG_CW
+#define EWDG_CW 40
+#endif
 #ifndef EWDG_OCC32
 #define EWDG_OCC32 4
 #endif
@@ -392,12 +395,22 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     o[0] = 0;
     o[1] = 0;
     o[2] = 0;
-#pragma unroll 8
-    for (int j = 0; j < Np; ++j) {
-      const T w = Wm[j * Np];
-      o[0] += w * Srv[j * SV + e];
-      o[1] += w * Srv[j * SV + 16 + e];
-      o[2] += w * Srv[j * SV + 32 + e];
+    // W column in chunks whose loads issue together (one round trip per chunk)
+    constexpr int CW = Np < EWDG_CW ? Np : EWDG_CW;
+#pragma unroll
+    for (int j0 = 0; j0 < Np; j0 += CW) {
+      T w[CW];
+#pragma unroll
+      for (int u = 0; u < CW; ++u) w[u] = (j0 + u < Np) ? Wm[(j0 + u) * Np] : T(0);
+#pragma unroll
+      for (int u = 0; u < CW; ++u) {
+        if (j0 + u < Np) {
+          const int j = j0 + u;
+          o[0] += w[u] * Srv[j * SV + e];
+          o[1] += w[u] * Srv[j * SV + 16 + e];
+          o[2] += w[u] * Srv[j * SV + 32 + e];
+        }
+      }
     }
     if (ge == a.src_elem) {
       const T sv = a.srcval * a.svec[i];
