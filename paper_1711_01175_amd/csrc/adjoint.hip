@@ -321,7 +321,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
 #pragma unroll
       for (int m = 0; m < 6; ++m) tau[m] += p * SB[(e * 6 + m) * Np + i];
     }
-    const T lam = a.lm[(e0 + e) * 2 * Nq + qp], mu = a.lm[(e0 + e) * 2 * Nq + Nq + qp];
+    const T lam = a.lm[(e0 + e) * 2 * S::NqP + qp], mu = a.lm[(e0 + e) * 2 * S::NqP + S::NqP + qp];
     const T trt = tau[0] + tau[1] + tau[2];
 #pragma unroll
     for (int m = 0; m < 6; ++m) Qd[(e * 6 + m) * Nq + qp] = T(2) * mu * tau[m] + (m < 3 ? lam * trt : T(0));

@@ -107,7 +107,7 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.scratch = scratch;
   d.scratch_bytes = off - scratch_begin;
   d.W = take(Np * Np * K * ts);
-  d.lm = take(2 * Nq * K * ts);
+  d.lm = take(2 * ((Nq + 3) / 4 * 4) * K * ts);
   d.geo = take(9 * K * ts);
   d.fgeo = take(16 * K * ts);
   d.Z = take(2 * K * ts);

@@ -17,7 +17,7 @@ struct Dev {
   void* s[2] = {nullptr, nullptr};   // [K][6][Np] sigma_h of q[i]
   void* res = nullptr;               // [K][9][Np] LSRK register
   void* W = nullptr;                 // [K][Np][Np], W[k][j][i] = (M_rho^-1 M)_ij
-  void* lm = nullptr;                // [K][2][Nq] lambda, mu at quadrature points
+  void* lm = nullptr;                // [K][2][NqP] lambda, mu at quadrature points (NqP = Nq rounded up to 4, zero padded)
   void* geo = nullptr;               // [K][9] dr_i/dx_j
   void* fgeo = nullptr;              // [K][4][4] n_x, n_y, n_z, Fscale
   void* Z = nullptr;                 // [K][2] Z_p, Z_s

@@ -9,6 +9,7 @@ struct Sz {
   static constexpr int Nfp = (N + 1) * (N + 2) / 2;            // nodes of one face
   static constexpr int Nq = (N + 1) * (N + 1) * (N + 1);       // quadrature points
   static constexpr int NF = 4 * Nfp;
+  static constexpr int NqP = (Nq + 3) / 4 * 4;                 // padded stride of lambda, mu
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int BUF = cmax(9 * Np, cmax(9 * NF, 6 * Nq));
 };

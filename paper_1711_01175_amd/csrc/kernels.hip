@@ -63,7 +63,7 @@ constexpr int cmax2(int a, int b) { return a > b ? a : b; }
 template <int N>
 struct Tile {
   using S = Sz<N>;
-  static constexpr int Np = S::Np, Nfp = S::Nfp, Nq = S::Nq;
+  static constexpr int Np = S::Np, Nfp = S::Nfp, Nq = S::Nq, NqP = S::NqP;
   static constexpr int E = 16;
   static constexpr int NpK = ceil_to(Np, 4);    // node index as the K dimension
   static constexpr int NpR = ceil_to(Np, 16);   // node index as the row dimension
@@ -468,12 +468,24 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       // unconditional loads from clamped (valid) indices, masked after
       const int gc = ge < Ke ? ge : Ke - 1;
       T lam[4], mu2[4];
+      constexpr int NqP = TL::NqP;
+      const T* lmr = a.lm + static_cast<int64_t>(gc) * 2 * NqP;
+      if constexpr (sizeof(T) == 4) {
+        // rows 4 lg .. 4 lg + 3 of the tile are contiguous: one 16-byte load each
+        const int q4 = Rq * 16 + 4 * lg;
+        const int qs = q4 + 4 <= NqP ? q4 : NqP - 4;
+        const float4 l4 = *reinterpret_cast<const float4*>(lmr + qs);
+        const float4 m4 = *reinterpret_cast<const float4*>(lmr + NqP + qs);
+        lam[0] = l4.x; lam[1] = l4.y; lam[2] = l4.z; lam[3] = l4.w;
+        mu2[0] = T(2) * m4.x; mu2[1] = T(2) * m4.y; mu2[2] = T(2) * m4.z; mu2[3] = T(2) * m4.w;
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = Rq * 16 + M::row(lg, r);
-        const int qq = q < Nq ? q : Nq - 1;
-        lam[r] = a.lm[gc * 2 * Nq + qq];
-        mu2[r] = T(2) * a.lm[gc * 2 * Nq + Nq + qq];
+        for (int r = 0; r < 4; ++r) {
+          const int q = Rq * 16 + M::row(lg, r);
+          const int qq = q < Nq ? q : Nq - 1;
+          lam[r] = lmr[qq];
+          mu2[r] = T(2) * lmr[NqP + qq];
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -581,7 +593,7 @@ __global__ __launch_bounds__(256) void k_sigma(const T* __restrict__ q, T* __res
       const T vv = VqT[j * Nq + qp];
       for (int m = 0; m < 6; ++m) ep[m] += vv * se[m * Np + j];
     }
-    const T lam = lm[e * 2 * Nq + qp], mu = lm[e * 2 * Nq + Nq + qp];
+    const T lam = lm[e * 2 * S::NqP + qp], mu = lm[e * 2 * S::NqP + S::NqP + qp];
     const T ltr = lam * (ep[0] + ep[1] + ep[2]);
     for (int m = 0; m < 6; ++m) sg[m * Nq + qp] = T(2) * mu * ep[m] + (m < 3 ? ltr : T(0));
   }
@@ -653,12 +665,17 @@ __global__ __launch_bounds__(256) void k_material(Dev d, int64_t e_begin) {
     W[j * Np + i] = static_cast<T>(acc);
   }
   // run-precision lambda, mu and the impedances from the element means
-  T* lm = static_cast<T*>(d.lm) + e * 2 * Nq;
+  constexpr int NqP = S::NqP;
+  T* lm = static_cast<T*>(d.lm) + e * 2 * NqP;
+  for (int q = Nq + threadIdx.x; q < NqP; q += blockDim.x) {
+    lm[q] = T(0);
+    lm[NqP + q] = T(0);
+  }
   double a0 = 0, a1 = 0, a2 = 0;
   for (int q = threadIdx.x; q < Nq; q += blockDim.x) {
     const double w = d.wq64[q];
     lm[q] = static_cast<T>(d.lam64[e * Nq + q]);
-    lm[Nq + q] = static_cast<T>(d.mu64[e * Nq + q]);
+    lm[NqP + q] = static_cast<T>(d.mu64[e * Nq + q]);
     a0 += w * d.rho64[e * Nq + q];
     a1 += w * d.lam64[e * Nq + q];
     a2 += w * d.mu64[e * Nq + q];
