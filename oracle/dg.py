@@ -87,9 +87,13 @@ class Elastic:
         if min(self.rho_q.real.min(), self.mu_q.real.min()) <= 0 or self.lam_q.real.min() < 0:
             raise ValueError("material must satisfy rho, mu > 0, lambda >= 0")
         w = R.wq
-        # Density-weighted mass M_rho[k] = J_k (rho psi_m, psi_n)_Q.
-        self.Mrho = M.J[:, None, None] * np.einsum('qm,kq,qn->kmn', R.Psi_q,
-                                                   w[None, :] * self.rho_q, R.Psi_q)
+        # Density-weighted mass M_rho[k] = J_k (rho psi_m, psi_n)_Q, i.e.
+        # J_k Psi^T diag(w rho_k) Psi, formed in element chunks as products.
+        self.Mrho = np.empty((self.K, self.Np, self.Np), dtype=dt_)
+        for k0 in range(0, self.K, 4096):
+            k1 = min(k0 + 4096, self.K)
+            wr = (w[None, :] * self.rho_q[k0:k1])[:, :, None] * R.Psi_q[None, :, :]   # [k][q][n]
+            self.Mrho[k0:k1] = M.J[k0:k1, None, None] * (R.Psi_q.T[None, :, :] @ wr)
         self.Mrho_inv = np.linalg.inv(self.Mrho)
         wsum = w.sum()
         self.rho_bar = self.rho_q @ w / wsum
