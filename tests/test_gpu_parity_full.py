@@ -1,0 +1,164 @@
+"""GPU parity at the workloads' full sizes and over long runs.
+
+* 1000 LSRK steps on the heterogeneous cube (n=3, N=4, Ricker source) against
+  the oracle's state stored by tests/golden/long_run_n3_N4.py: relative L2 at
+  the quadrature points <= 1e-12 (FP64) and <= 1e-5 (FP32).
+* Heterogeneous cube 32^3 x 6 = 196,608 tets, N=4 (the bench workload): one
+  right-hand side of a random state with the source on, compared with the
+  oracle on 64 sampled elements (the oracle is built for the whole mesh and
+  evaluates only those elements).
+* High order: 16^3 x 6 = 24,576 tets, N=7, smooth media with seeded +-10 %
+  per-element perturbations: sampled right-hand-side parity, and 500 steps in
+  FP32 against FP64 (reported; FP32 held within 1e-4).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection, outside the per-test time limit)
+
+from helpers import quad_points
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "long_run_n3_N4.npz")
+SRC = dict(xs=[0.05, -0.10, 0.15], direction=[0.0, 0.0, 1.0], amp=1.0, f0=5.0, t0=0.2)
+TOL = {64: 1e-12, 32: 1e-5}
+
+
+def _report(name, **kw):
+    print(name, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}" for k, v in kw.items()),
+          flush=True)
+
+
+def _ctx(N, prec, EToV, VXYZ, mat):
+    import paper_1711_01175_amd as P
+    c = P.Context(N, prec)
+    c.set_mesh(EToV, VXYZ)
+    c.bind_workspace()
+    c.set_material(*mat)
+    c.set_source(SRC["xs"], SRC["direction"], SRC["amp"], SRC["f0"], SRC["t0"])
+    return c
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_long_run_1000_steps(prec):
+    import torch
+
+    from oracle.dg import Elastic
+    from oracle.reference import stroud_rule
+    from workloads import media
+    from workloads.mesh import kuhn_periodic_mesh
+    g = np.load(GOLDEN)
+    N, nsteps = 4, int(g["nsteps"])
+    EToV, VXYZ = kuhn_periodic_mesh(3)
+    xyz = quad_points(VXYZ, stroud_rule(N)[0])
+    mat = media.smooth(xyz)
+    op = Elastic(N, VXYZ, *mat)
+    c = _ctx(N, prec, EToV, VXYZ, mat)
+    c.set_state(torch.zeros((c.K, 9, c.Np), dtype=c.torch_dtype, device="cuda"), 0.0)
+    dt = c.cfl_dt(0.5)
+    assert abs(dt - float(g["dt"])) <= 1e-15 * dt
+    c.step(dt, nsteps)
+    got = c.eval_quadrature().cpu().numpy()
+    ref = op.to_q(g["c"])
+    err = op.l2_q(got - ref) / op.l2_q(ref)
+    _report("long", prec=prec, steps=nsteps, rel_l2=float(err), energy=c.energy(), energy_oracle=float(g["energy"]))
+    assert err <= TOL[prec]
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def cube32():
+    from oracle.dg import Elastic
+    from oracle.reference import stroud_rule
+    from workloads import media
+    from workloads.mesh import kuhn_periodic_mesh
+    N = 4
+    EToV, VXYZ = kuhn_periodic_mesh(32)
+    xyz = quad_points(VXYZ, stroud_rule(N)[0])
+    mat = media.smooth(xyz)
+    del xyz
+    op = Elastic(N, VXYZ, *mat)
+    op.set_source(SRC["xs"], SRC["direction"], SRC["amp"])
+    rng = np.random.default_rng(32)
+    cm = rng.standard_normal((op.K, 9, op.Np))
+    src_elem = int(op.mesh.locate(np.array(SRC["xs"]))[0])
+    elems = np.unique(np.concatenate([[src_elem, 0, op.K - 1], rng.choice(op.K, 61, replace=False)]))
+    return dict(N=N, EToV=EToV, VXYZ=VXYZ, mat=mat, op=op, cm=cm, elems=elems)
+
+
+def _sampled_rhs(case, prec, t=0.23):
+    import torch
+
+    from oracle.timestep import ricker
+    op, elems = case["op"], case["elems"]
+    c = _ctx(case["N"], prec, case["EToV"], case["VXYZ"], case["mat"])
+    # the same degree-N state on both sides: oracle modal coefficients, handed
+    # to the GPU as values at the quadrature points (exactly representable)
+    fq = torch.from_numpy(op.to_q(case["cm"]))
+    q = c.project_quadrature(fq)
+    del fq
+    rq = c.eval_quadrature(c.rhs(t, q))
+    got = rq[torch.as_tensor(elems, device=rq.device)].cpu().numpy()
+    del rq, q
+    c.close()
+    torch.cuda.empty_cache()
+    ref = op.to_q(op.rhs(case["cm"], src_value=ricker(t, SRC["f0"], SRC["t0"]), elems=elems))
+    w = op.ref.wq[None, None, :] * op.mesh.J[elems][:, None, None]
+    return float(np.sqrt(np.sum(w * (got - ref) ** 2) / np.sum(w * ref ** 2)))
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec", [64, 32])
+def test_heterogeneous_cube_full_size_rhs_sampled(cube32, prec):
+    err = _sampled_rhs(cube32, prec)
+    _report("cube32", prec=prec, K=cube32["op"].K, sampled=len(cube32["elems"]), rel_l2=err)
+    assert err <= TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def high_order():
+    from oracle.dg import Elastic
+    from oracle.reference import stroud_rule
+    from workloads import media
+    from workloads.mesh import kuhn_periodic_mesh
+    N = 7
+    EToV, VXYZ = kuhn_periodic_mesh(16)
+    xyz = quad_points(VXYZ, stroud_rule(N)[0])
+    mat = media.perturb_per_element(*media.smooth(xyz), 3, frac=0.1)
+    del xyz
+    op = Elastic(N, VXYZ, *mat)
+    op.set_source(SRC["xs"], SRC["direction"], SRC["amp"])
+    rng = np.random.default_rng(7)
+    cm = rng.standard_normal((op.K, 9, op.Np))
+    src_elem = int(op.mesh.locate(np.array(SRC["xs"]))[0])
+    elems = np.unique(np.concatenate([[src_elem, 0, op.K - 1], rng.choice(op.K, 29, replace=False)]))
+    return dict(N=N, EToV=EToV, VXYZ=VXYZ, mat=mat, op=op, cm=cm, elems=elems)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec", [64, 32])
+def test_high_order_full_size_rhs_sampled(high_order, prec):
+    err = _sampled_rhs(high_order, prec)
+    _report("N7", prec=prec, K=high_order["op"].K, sampled=len(high_order["elems"]), rel_l2=err)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.timeout(300)
+def test_high_order_500_steps_fp32_vs_fp64(high_order):
+    import torch
+    case, states, energies = high_order, {}, {}
+    for prec in (64, 32):
+        c = _ctx(case["N"], prec, case["EToV"], case["VXYZ"], case["mat"])
+        c.set_state(torch.zeros((c.K, 9, c.Np), dtype=c.torch_dtype, device="cuda"), 0.0)
+        dt = c.cfl_dt(0.5)
+        c.step(dt, 500)
+        states[prec] = c.eval_quadrature().cpu().numpy()
+        energies[prec] = c.energy()
+        c.close()
+        torch.cuda.empty_cache()
+    op = case["op"]
+    err = op.l2_q(states[32] - states[64]) / op.l2_q(states[64])
+    _report("N7-500", rel_l2_fp32_vs_fp64=float(err), energy64=energies[64], energy32=energies[32])
+    assert err <= 1e-4
