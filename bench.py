@@ -141,10 +141,22 @@ def run_serving(full=False):
     else:
         kw = dict(count=64, n_range=(6, 14), nsteps=100)
     budget, slots = 16 << 30, 32
-    calib = Server(budget, slots=slots, precision=32).run(request_stream(**kw))
+
+    def progress(tag):
+        last = [0.0]
+
+        def cb(done, total, elapsed):
+            if elapsed - last[0] >= 20.0 or done == total:
+                last[0] = elapsed
+                print(f"serving {tag}: {done}/{total} requests done at {elapsed:.1f} s", file=sys.stderr,
+                      flush=True)
+        return cb
+
+    calib = Server(budget, slots=slots, precision=32).run(request_stream(**kw), progress=progress("calibration"))
     sat = len(calib.results) / calib.makespan
     rate = 0.8 * sat
-    stats = Server(budget, slots=slots, precision=32).run(request_stream(rate=rate, **kw))
+    stats = Server(budget, slots=slots, precision=32).run(request_stream(rate=rate, **kw),
+                                                          progress=progress("poisson"))
     out = stats.summary()
     out.update({"workload": f"{kw['count']} requests, n~U{{{kw['n_range'][0]}..{kw['n_range'][1]}}} hexes/axis x 6 tets, "
                             f"N~U{{3,4,5}}, {kw['nsteps']} LSRK steps each, FP32, random media and source per request, "

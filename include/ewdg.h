@@ -188,7 +188,7 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
  * at most max_steps recorded steps with a checkpoint of (q, sigma_h) every
  * checkpoint_every steps; it holds ceil(max_steps/checkpoint_every)
  * checkpoints plus checkpoint_every step-start states of one segment, about
- * (ceil(max_steps/C) + C + 13) * 15 K Np values in the run precision.  Call
+ * (ceil(max_steps/C) + C + 11) * 15 K Np values in the run precision.  Call
  * after ewdg_bind_workspace (the receiver capacity is taken from it);
  * binding the forward workspace again or a new mesh drops the binding. */
 int ewdg_adjoint_workspace_bytes(const ewdg_ctx* ctx, int max_steps, int checkpoint_every, size_t* bytes);

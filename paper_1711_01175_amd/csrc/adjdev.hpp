@@ -16,7 +16,8 @@ struct AdjDev {
   void* fnbr = nullptr;      // [K][4][Nfp][8] neighbour-side face sensitivities
   void* qbar = nullptr;      // [K][9][Np] adjoint of the state
   void* rbar = nullptr;      // [K][9][Np] adjoint of the LSRK register
-  void* rhs = nullptr;       // [K][9][Np] L q + f of the current stage input
+  void* rhs = nullptr;       // [K][9][Np] L q + f (single right-hand-side adjoint)
+  void* rhsv = nullptr;      // [5][K][3][Np] velocity rows of L q_i + f_i of one step
   void* res = nullptr;       // [K][9][Np] LSRK register of the recomputation
   double* g = nullptr;       // [K][3] parameter gradient
   double* resid = nullptr;   // [nsteps][nr][3] receiver residuals
@@ -31,9 +32,10 @@ struct AdjDev {
 };
 
 // qbar += scale * L^T y; if q is given also g += scale * y . d(L q + f)/d theta
-// (s = sigma_h(q), rhs = L q + f).
+// (s = sigma_h(q); rhs holds the velocity rows of L q + f at element stride
+// rhs_stride values, component c at offset c Np).
 hipError_t launch_adjoint(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
-                          const void* rhs, void* qbar, double* g, double scale, hipStream_t st);
+                          const void* rhs, int rhs_stride, void* qbar, double* g, double scale, hipStream_t st);
 // qbar_v += scale * (receiver basis row)^T resid for every receiver
 hipError_t launch_adj_receivers(const Dev& d, void* qbar, const double* resid, int nr, double scale,
                                 hipStream_t st);

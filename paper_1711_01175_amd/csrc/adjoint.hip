@@ -22,7 +22,8 @@ struct AdjArgs {
   const T* y;          // [K][9][Np] adjoint of the stage right-hand side
   const T* q;          // forward stage input [K][9][Np] (null: no parameter gradient)
   const T* s;          // sigma_h(q) [K][6][Np]
-  const T* rhs;        // L q + f [K][9][Np] (density gradient)
+  const T* rhs;        // velocity rows of L q + f, element stride rhs_es (density gradient)
+  int rhs_es;
   T* ytil;             // [K][3][Np] W^T y_v
   T* fown;             // [K][4][Nfp][8] own-side sensitivities (v, T, Z_p, Z_s)
   T* fnbr;             // [K][4][Nfp][8] neighbour-side sensitivities
@@ -358,7 +359,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
       T p = 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        p += a.y[(e0 + e) * 9 * Np + c * Np + j] * a.rhs[(e0 + e) * 9 * Np + c * Np + j];
+        p += a.y[(e0 + e) * 9 * Np + c * Np + j] * a.rhs[(e0 + e) * a.rhs_es + c * Np + j];
       pr[e * Np + j] = -p;
     }
   }
@@ -418,12 +419,13 @@ __global__ __launch_bounds__(256) void k_scal(T* y, T a, int64_t n) {
 
 template <typename T>
 static AdjArgs<T> adj_args(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
-                           const void* rhs, void* qbar, double* g, double scale) {
+                           const void* rhs, int rhs_es, void* qbar, double* g, double scale) {
   AdjArgs<T> a;
   a.y = static_cast<const T*>(y);
   a.q = static_cast<const T*>(q);
   a.s = static_cast<const T*>(s);
   a.rhs = static_cast<const T*>(rhs);
+  a.rhs_es = rhs_es;
   a.ytil = static_cast<T*>(ad.ytil);
   a.fown = static_cast<T*>(ad.fown);
   a.fnbr = static_cast<T*>(ad.fnbr);
@@ -451,9 +453,10 @@ static AdjArgs<T> adj_args(const Dev& d, const AdjDev& ad, const void* y, const 
 
 template <typename T, int N>
 static hipError_t adjoint_impl(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
-                               const void* rhs, void* qbar, double* g, double scale, hipStream_t st) {
+                               const void* rhs, int rhs_es, void* qbar, double* g, double scale,
+                               hipStream_t st) {
   using C = AdjCfg<T, N>;
-  const AdjArgs<T> a = adj_args<T>(d, ad, y, q, s, rhs, qbar, g, scale);
+  const AdjArgs<T> a = adj_args<T>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale);
   const unsigned grid = static_cast<unsigned>((d.K + C::E - 1) / C::E);
   hipLaunchKernelGGL((k_adjA<T, N>), dim3(grid), dim3(C::NT), 0, st, a);
   hipError_t e = hipGetLastError();
@@ -463,11 +466,11 @@ static hipError_t adjoint_impl(const Dev& d, const AdjDev& ad, const void* y, co
 }
 
 hipError_t launch_adjoint(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
-                          const void* rhs, void* qbar, double* g, double scale, hipStream_t st) {
+                          const void* rhs, int rhs_es, void* qbar, double* g, double scale, hipStream_t st) {
   if (d.prec == 32) {
-    EWDG_DISPATCH(d.N, return (adjoint_impl<float, NN>(d, ad, y, q, s, rhs, qbar, g, scale, st)));
+    EWDG_DISPATCH(d.N, return (adjoint_impl<float, NN>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale, st)));
   }
-  EWDG_DISPATCH(d.N, return (adjoint_impl<double, NN>(d, ad, y, q, s, rhs, qbar, g, scale, st)));
+  EWDG_DISPATCH(d.N, return (adjoint_impl<double, NN>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale, st)));
 }
 
 hipError_t launch_adj_receivers(const Dev& d, void* qbar, const double* resid, int nr, double scale,

@@ -779,6 +779,7 @@ size_t adj_layout(const ewdg_ctx* c, int max_steps, int every, int max_rec, char
   a.qbar = take(9 * Np * K * ts);
   a.rbar = take(9 * Np * K * ts);
   a.rhs = take(9 * Np * K * ts);
+  a.rhsv = take(5 * 3 * Np * K * ts);
   a.res = take(9 * Np * K * ts);
   a.g = reinterpret_cast<double*>(take(3 * K * 8));
   a.resid = reinterpret_cast<double*>(take(static_cast<size_t>(max_steps) * (max_rec > 0 ? max_rec : 1) * 3 * 8));
@@ -786,8 +787,8 @@ size_t adj_layout(const ewdg_ctx* c, int max_steps, int every, int max_rec, char
   a.ck_s = take(nck * 6 * Np * K * ts);
   a.seg_q = take(static_cast<size_t>(every) * 9 * Np * K * ts);
   a.seg_s = take(static_cast<size_t>(every) * 6 * Np * K * ts);
-  a.st_q = take(4 * 9 * Np * K * ts);
-  a.st_s = take(4 * 6 * Np * K * ts);
+  a.st_q = take(5 * 9 * Np * K * ts);
+  a.st_s = take(5 * 6 * Np * K * ts);
   if (ad) *ad = a;
   return off;
 }
@@ -802,10 +803,13 @@ int copy_dev(ewdg_ctx* c, void* dst, const void* src, int m) {
   return c->hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "snapshot copy");
 }
 
-// One LSRK stage on caller buffers (the context state is untouched).
-int stage_on(ewdg_ctx* c, int i, double dt, double tn, const void* qin, const void* sin, void* qout, void* sout) {
+// One LSRK stage on caller buffers (the context state is untouched); with
+// rhsv the velocity rows of the stage's right-hand side are kept as well.
+int stage_on(ewdg_ctx* c, int i, double dt, double tn, const void* qin, const void* sin, void* qout, void* sout,
+             void* rhsv = nullptr) {
   const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, tn + kRkC[i] * dt);
-  return c->hip(launch_stage(c->d, 1, qin, sin, qout, sout, c->ad.res, sc, c->stream), "recompute stage");
+  return c->hip(launch_stage(c->d, rhsv ? 2 : 1, qin, sin, qout, sout, c->ad.res, sc, c->stream, rhsv),
+                "recompute stage");
 }
 
 int need_adj(ewdg_ctx* c) {
@@ -862,7 +866,7 @@ int ewdg_rhs_adjoint(ewdg_ctx* c, double t, const void* q, const void* y, void* 
   if (g) {
     if ((rc = c->hip(hipMemsetAsync(g, 0, 3 * static_cast<size_t>(c->mesh.K) * 8, c->stream), "memset"))) return rc;
   }
-  return c->hip(launch_adjoint(c->d, c->ad, y, q, s, c->ad.rhs, LTy, g, 1.0, c->stream), "adjoint");
+  return c->hip(launch_adjoint(c->d, c->ad, y, q, s, c->ad.rhs, 9 * c->re.Np, LTy, g, 1.0, c->stream), "adjoint");
 }
 
 int ewdg_forward_misfit(ewdg_ctx* c, double dt, int nsteps, const double* data, double* J) {
@@ -945,11 +949,14 @@ int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
                                               c->stream), "adjoint receivers")))
           return rc;
       }
-      // stage inputs q_1..q_4 of step n
+      // stage inputs q_1..q_4 of step n and the velocity rows of every
+      // stage's right-hand side (the fifth stage's output is not needed)
       const void* qi = slot(a.seg_q, c, 9, m);
       const void* si = slot(a.seg_s, c, 6, m);
-      for (int i = 0; i < 4; ++i) {
-        if ((rc = stage_on(c, i, dt, tn, qi, si, slot(a.st_q, c, 9, i), slot(a.st_s, c, 6, i)))) return rc;
+      for (int i = 0; i < 5; ++i) {
+        if ((rc = stage_on(c, i, dt, tn, qi, si, slot(a.st_q, c, 9, i), slot(a.st_s, c, 6, i),
+                           slot(a.rhsv, c, 3, i))))
+          return rc;
         qi = slot(a.st_q, c, 9, i);
         si = slot(a.st_s, c, 6, i);
       }
@@ -958,9 +965,9 @@ int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
         const void* sin = i == 0 ? slot(a.seg_s, c, 6, m) : slot(a.st_s, c, 6, i - 1);
         if ((rc = c->hip(launch_axpy(c->prec, a.rbar, a.qbar, kRkB[i], static_cast<int64_t>(n9), c->stream), "axpy")))
           return rc;
-        const StageCoef sc = coef(c, 0.0, 0.0, 0.0, tn + kRkC[i] * dt);
-        if ((rc = c->hip(launch_stage(c->d, 0, qin, sin, nullptr, nullptr, a.rhs, sc, c->stream), "rhs"))) return rc;
-        if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, qin, sin, a.rhs, a.qbar, a.g, dt, c->stream), "adjoint")))
+        if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, qin, sin, slot(a.rhsv, c, 3, i), 3 * c->re.Np, a.qbar,
+                                        a.g, dt, c->stream),
+                         "adjoint")))
           return rc;
         if ((rc = c->hip(launch_scal(c->prec, a.rbar, kRkA[i], static_cast<int64_t>(n9), c->stream), "scal")))
           return rc;

@@ -73,9 +73,10 @@ struct StageCoef {
 hipError_t launch_material(const Dev& d, hipStream_t st);
 hipError_t launch_source_vector(const Dev& d, int64_t elem, hipStream_t st);
 hipError_t launch_sigma(const Dev& d, const void* q, void* s, hipStream_t st);
-// mode 0: rhs = L(qin) written to out; mode 1: LSRK stage, qin/sin -> qout/sout
+// mode 0: rhs = L(qin) written to out; mode 1: LSRK stage, qin/sin -> qout/sout;
+// mode 2: as mode 1, and the velocity rows of L(qin) + f go to rhsv [K][3][Np]
 hipError_t launch_stage(const Dev& d, int mode, const void* qin, const void* sin, void* qout,
-                        void* sout, void* out, const StageCoef& c, hipStream_t st);
+                        void* sout, void* out, const StageCoef& c, hipStream_t st, void* rhsv = nullptr);
 hipError_t launch_project(const Dev& d, const double* fq, void* q, hipStream_t st);
 hipError_t launch_evalq(const Dev& d, const void* q, double* fq, hipStream_t st);
 hipError_t launch_receivers(const Dev& d, const void* q, int nr, int step, hipStream_t st);

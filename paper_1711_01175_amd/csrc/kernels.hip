@@ -92,7 +92,8 @@ struct StageArgs {
   const T* sin;
   T* qout;
   T* sout;
-  T* out;        // rhs (mode 0) or the LSRK register (mode 1)
+  T* out;        // rhs (mode 0) or the LSRK register (modes 1, 2)
+  T* rhsv;       // mode 2: the velocity rows of the right-hand side [K][3][Np]
   const T* W;
   const T* lm;
   const T* geo;
@@ -388,8 +389,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     T rv[9], qv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      rv[c] = (MODE == 1) ? a.out[base + c * Np] : T(0);
-      qv[c] = (MODE == 1) ? a.qin[base + c * Np] : T(0);
+      rv[c] = (MODE != 0) ? a.out[base + c * Np] : T(0);
+      qv[c] = (MODE != 0) ? a.qin[base + c * Np] : T(0);
     }
     T o[9];
     o[0] = 0;
@@ -417,6 +418,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       o[0] += sv * a.dir0;
       o[1] += sv * a.dir1;
       o[2] += sv * a.dir2;
+    }
+    if (MODE == 2) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.rhsv[static_cast<int64_t>(ge) * 3 * Np + c * Np + i] = o[c];
     }
 #pragma unroll
     for (int m = 0; m < 6; ++m) o[3 + m] = Se[i * SE + m * 16 + e];
@@ -820,13 +825,14 @@ __global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ x, int6
 // ------------------------------------------------------------------ launchers
 template <typename T>
 static StageArgs<T> stage_args(const Dev& d, const void* qin, const void* sin, void* qout,
-                               void* sout, void* out, const StageCoef& c) {
+                               void* sout, void* out, const StageCoef& c, void* rhsv = nullptr) {
   StageArgs<T> a;
   a.qin = static_cast<const T*>(qin);
   a.sin = static_cast<const T*>(sin);
   a.qout = static_cast<T*>(qout);
   a.sout = static_cast<T*>(sout);
   a.out = static_cast<T*>(out);
+  a.rhsv = static_cast<T*>(rhsv);
   a.W = static_cast<const T*>(d.W);
   a.lm = static_cast<const T*>(d.lm);
   a.geo = static_cast<const T*>(d.geo);
@@ -854,18 +860,21 @@ static StageArgs<T> stage_args(const Dev& d, const void* qin, const void* sin, v
 
 template <typename T, int N>
 static hipError_t stage_impl(const Dev& d, int mode, const void* qin, const void* sin, void* qout,
-                             void* sout, void* out, const StageCoef& c, hipStream_t st) {
+                             void* sout, void* out, const StageCoef& c, void* rhsv, hipStream_t st) {
   using TL = Tile<N>;
   // the stage kernel indexes its arrays with 32-bit element offsets
   if (d.K * 9 * TL::Np >= (int64_t(1) << 31) || d.K * TL::Np * TL::Np >= (int64_t(1) << 31) ||
-      d.K * 2 * TL::Nq >= (int64_t(1) << 31))
+      d.K * 2 * TL::NqP >= (int64_t(1) << 31))
     return hipErrorInvalidValue;
-  const StageArgs<T> a = stage_args<T>(d, qin, sin, qout, sout, out, c);
+  if (mode == 2 && !rhsv) return hipErrorInvalidValue;
+  const StageArgs<T> a = stage_args<T>(d, qin, sin, qout, sout, out, c, rhsv);
   const unsigned grid = static_cast<unsigned>((d.K + TL::E - 1) / TL::E);
   if (mode == 0)
     hipLaunchKernelGGL((k_stage<T, N, 0>), dim3(grid), dim3(TL::NT), 0, st, a);
-  else
+  else if (mode == 1)
     hipLaunchKernelGGL((k_stage<T, N, 1>), dim3(grid), dim3(TL::NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_stage<T, N, 2>), dim3(grid), dim3(TL::NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -940,9 +949,11 @@ hipError_t launch_sigma(const Dev& d, const void* q, void* s, hipStream_t st) {
 }
 
 hipError_t launch_stage(const Dev& d, int mode, const void* qin, const void* sin, void* qout, void* sout,
-                        void* out, const StageCoef& c, hipStream_t st) {
-  if (d.prec == 32) { EWDG_DISPATCH(d.N, return (stage_impl<float, NN>(d, mode, qin, sin, qout, sout, out, c, st))); }
-  EWDG_DISPATCH(d.N, return (stage_impl<double, NN>(d, mode, qin, sin, qout, sout, out, c, st)));
+                        void* out, const StageCoef& c, hipStream_t st, void* rhsv) {
+  if (d.prec == 32) {
+    EWDG_DISPATCH(d.N, return (stage_impl<float, NN>(d, mode, qin, sin, qout, sout, out, c, rhsv, st)));
+  }
+  EWDG_DISPATCH(d.N, return (stage_impl<double, NN>(d, mode, qin, sin, qout, sout, out, c, rhsv, st)));
 }
 
 hipError_t launch_project(const Dev& d, const double* fq, void* q, hipStream_t st) {

@@ -10,6 +10,9 @@ while others run join the same launches at the next chunk boundary.  Each
 request's arithmetic is identical to a solo run, so results do not depend on
 the mix.
 
+Host preparation of arrived requests (worker threads) and device setup of
+admitted ones (a side stream) overlap the running chunk.
+
 Only orchestration lives here; every step of the method runs in libewdg.
 """
 import time
@@ -53,6 +56,7 @@ class _Live:
     done: int = 0
     t_admit: float = 0.0
     ws: object = None
+    material: object = None
 
 
 @dataclass
@@ -95,11 +99,20 @@ class ServeStats:
 
 
 class Server:
-    """Admission by HBM footprint, continuous batching, per-request results."""
+    """Admission by HBM footprint, continuous batching, per-request results.
+
+    Three things overlap the device work of a running chunk: host preparation
+    of arrived requests (mesh, quadrature points, sampled media) in worker
+    threads, device setup of admitted requests (workspace, FP64 material
+    setup) on a side stream, and the bookkeeping of retired requests.  All
+    chunks run on one stream of their own; admitted requests join the next
+    chunk.
+    """
 
     def __init__(self, budget_bytes, slots=32, precision=32, chunk_steps=10, cfl=0.5,
-                 keep_state=False):
+                 keep_state=False, prep_workers=4):
         import torch
+        from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
         self.budget = int(budget_bytes)
         self.slots = int(slots)
@@ -107,24 +120,34 @@ class Server:
         self.chunk = int(chunk_steps)
         self.cfl = float(cfl)
         self.keep_state = keep_state
-        self.stream = torch.cuda.current_stream()
+        self.stream = torch.cuda.Stream()          # chunks
+        self.setup_stream = torch.cuda.Stream()    # admissions
+        self.pool = ThreadPoolExecutor(max_workers=int(prep_workers))
         self.table = torch.empty(B.batch_table_bytes(self.slots), dtype=torch.uint8, device="cuda")
 
     def _prepare(self, req):
-        ctx = B.Context(req.N, self.precision, stream=self.stream.cuda_stream)
+        """Host only (worker thread): context, mesh, footprint, sampled media."""
+        ctx = B.Context(req.N, self.precision, stream=self.setup_stream.cuda_stream)
         ctx.set_mesh(*req.mesh())
         nr = len(req.receivers)
-        return _Live(req, ctx, ctx.workspace_bytes(nr, req.nsteps))
+        live = _Live(req, ctx, ctx.workspace_bytes(nr, req.nsteps))
+        live.material = req.material(ctx.quadrature_points())
+        return live
 
     def _start(self, live, now):
+        """Device setup on the side stream; returns when it is complete."""
         req, ctx = live.req, live.ctx
         nr = len(req.receivers)
-        live.ws = ctx.bind_workspace(nr, req.nsteps)
-        ctx.set_material(*req.material(ctx.quadrature_points()))
+        with self.torch.cuda.stream(self.setup_stream):
+            live.ws = ctx.bind_workspace(nr, req.nsteps)
+        ctx.set_material(*live.material)
+        live.material = None
         ctx.set_source(req.xs, req.direction, 1.0, req.f0, req.t0)
         if nr:
             ctx.set_receivers(req.receivers)
         live.dt = ctx.cfl_dt(self.cfl)
+        self.setup_stream.synchronize()
+        ctx.set_stream(self.stream.cuda_stream)
         live.t_admit = now
 
     def _finish(self, live, now, stats):
@@ -137,49 +160,71 @@ class Server:
         ctx.close()
         live.ws = None
 
-    def run(self, requests, clock=time.perf_counter, sleep=time.sleep):
-        """Serve requests arriving at req.arrival seconds after the start."""
+    def run(self, requests, clock=time.perf_counter, sleep=time.sleep, progress=None):
+        """Serve requests arriving at req.arrival seconds after the start.
+
+        progress: optional callable(done, total, elapsed_s) called whenever
+        requests complete."""
         stats = ServeStats()
+        total = len(requests)
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
-        waiting, active = deque(), []
+        waiting, active = deque(), []      # waiting: futures of prepared requests, FIFO
         used = 0
         t0 = clock()
         while pending or waiting or active:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
-                waiting.append(self._prepare(pending.popleft()))
-            adm, rej = admit_fifo([(id(w), w.footprint) for w in waiting], len(active), used,
+                waiting.append(self.pool.submit(self._prepare, pending.popleft()))
+            # launch the next chunk of everything active, then do host work
+            chunk = 0
+            if active:
+                chunk = min(self.chunk, min(a.req.nsteps - a.done for a in active))
+                B.step_batch([a.ctx for a in active], [a.dt for a in active], chunk, self.table,
+                             self.stream.cuda_stream)
+            # admission in arrival order among prepared requests (the head of
+            # the queue blocks the ones behind it until it is prepared)
+            ready = []
+            for f in waiting:
+                if not f.done():
+                    break
+                ready.append(f.result())
+            adm, rej = admit_fifo([(id(w), w.footprint) for w in ready], len(active), used,
                                   self.slots, self.budget)
-            for key in rej:
-                w = next(x for x in waiting if id(x) == key)
-                waiting.remove(w)
-                stats.rejected.append(w.req.rid)
-                w.ctx.close()
-            for key in adm:
-                w = next(x for x in waiting if id(x) == key)
-                waiting.remove(w)
-                self._start(w, clock() - t0)
-                used += w.footprint
-                active.append(w)
-            stats.max_used_bytes = max(stats.max_used_bytes, used)
-            stats.max_active = max(stats.max_active, len(active))
-            if not active:
-                if pending:
-                    sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.01)))
-                continue
-            chunk = min(self.chunk, min(a.req.nsteps - a.done for a in active))
-            B.step_batch([a.ctx for a in active], [a.dt for a in active], chunk, self.table,
-                         self.stream.cuda_stream)
-            self.stream.synchronize()
-            now = clock() - t0
-            still = []
-            for a in active:
-                a.done += chunk
-                if a.done >= a.req.nsteps:
-                    self._finish(a, now, stats)
-                    used -= a.footprint
+            admitted = []
+            for w in ready:
+                if id(w) in rej:
+                    stats.rejected.append(w.req.rid)
+                    w.ctx.close()
+                elif id(w) in adm:
+                    self._start(w, clock() - t0)
+                    used += w.footprint
+                    admitted.append(w)
                 else:
-                    still.append(a)
-            active = still
+                    break
+            for _ in range(sum(1 for w in ready if id(w) in rej or id(w) in adm)):
+                waiting.popleft()
+            stats.max_used_bytes = max(stats.max_used_bytes, used)
+            if chunk:
+                self.stream.synchronize()
+                now = clock() - t0
+                still, finished = [], 0
+                for a in active:
+                    a.done += chunk
+                    if a.done >= a.req.nsteps:
+                        self._finish(a, now, stats)
+                        used -= a.footprint
+                        finished += 1
+                    else:
+                        still.append(a)
+                active = still
+                if finished and progress is not None:
+                    progress(len(stats.results), total, now)
+            active += admitted
+            stats.max_active = max(stats.max_active, len(active))
+            if not active and not admitted:
+                if waiting:
+                    sleep(0.001)
+                elif pending:
+                    sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.01)))
         stats.makespan = clock() - t0
         return stats
