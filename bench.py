@@ -270,6 +270,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full 256-request stream (several minutes)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the FP32 adjoint leg and print its JSON (for profiling)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="time a plain device copy of 2 GiB instead (HBM calibration)")
     args = ap.parse_args()
@@ -281,6 +283,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.probe_copy:
         probe_copy()
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": run_adjoint(check_fp64=False)}), flush=True)
         return
     EToV, VXYZ, _ = build_workload(args.n, args.N)
     r32 = run_gpu(32, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)
