@@ -152,11 +152,14 @@ def run_serving(full=False):
                       flush=True)
         return cb
 
-    calib = Server(budget, slots=slots, precision=32).run(request_stream(**kw), progress=progress("calibration"))
+    srv = Server(budget, slots=slots, precision=32)
+    calib = srv.run(request_stream(**kw), progress=progress("calibration"))
+    srv.close()
     sat = len(calib.results) / calib.makespan
     rate = 0.8 * sat
-    stats = Server(budget, slots=slots, precision=32).run(request_stream(rate=rate, **kw),
-                                                          progress=progress("poisson"))
+    srv = Server(budget, slots=slots, precision=32)
+    stats = srv.run(request_stream(rate=rate, **kw), progress=progress("poisson"))
+    srv.close()
     out = stats.summary()
     out.update({"workload": f"{kw['count']} requests, n~U{{{kw['n_range'][0]}..{kw['n_range'][1]}}} hexes/axis x 6 tets, "
                             f"N~U{{3,4,5}}, {kw['nsteps']} LSRK steps each, FP32, random media and source per request, "

@@ -7,6 +7,13 @@
 #include "dev.hpp"
 #include "kcommon.hpp"
 
+// Tuning constants of the stage kernel (compile time; values measured on
+// MI355X at N=4):
+//  EWDG_SV, EWDG_SE, EWDG_SF, EWDG_SQ: LDS row strides (values) of the 3-,
+//    6-, 9- and 6-field operand buffers, 16 element columns per field;
+//  EWDG_QC: quadrature points per projection chunk;
+//  EWDG_CW: W_rho column values whose loads issue together;
+//  EWDG_OCC32: FP32 waves per SIMD asked of the register allocator.
 #ifndef EWDG_SV
 #define EWDG_SV 48
 #endif

@@ -125,6 +125,9 @@ class Server:
         self.pool = ThreadPoolExecutor(max_workers=int(prep_workers))
         self.table = torch.empty(B.batch_table_bytes(self.slots), dtype=torch.uint8, device="cuda")
 
+    def close(self):
+        self.pool.shutdown(wait=True)
+
     def _prepare(self, req):
         """Host only (worker thread): context, mesh, footprint, sampled media."""
         ctx = B.Context(req.N, self.precision, stream=self.setup_stream.cuda_stream)
