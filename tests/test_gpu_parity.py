@@ -147,3 +147,65 @@ def test_determinism_and_element_permutation():
     c.set_state(c.project_quadrature(torch.from_numpy(fq[perm])), 0.0)
     c.step(c.cfl_dt(0.5), 5)
     assert np.array_equal(c.get_state().cpu().numpy(), outs[0][perm])
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_constant_state_is_steady(prec):
+    """Degenerate case: a constant state in a homogeneous medium has zero
+    right-hand side (no gradients, no jumps)."""
+    torch = _torch()
+    from workloads import media
+    from workloads.mesh import kuhn_periodic_mesh
+    EToV, VXYZ = kuhn_periodic_mesh(3, shuffle_seed=5)
+    import paper_1711_01175_amd as P
+    c = P.Context(4, prec)
+    c.set_mesh(EToV, VXYZ)
+    c.bind_workspace()
+    c.set_material(*media.homogeneous(c.quadrature_points(), 1.3, 0.7, 1.1))
+    vals = np.array([0.3, -1.2, 0.5, 0.2, -0.1, 0.4, 0.15, -0.25, 0.05])
+    fq = torch.from_numpy(np.broadcast_to(vals[None, :, None], (c.K, 9, c.Nq)).copy())
+    q = c.project_quadrature(fq)
+    r = c.rhs(0.0, q)
+    # the exact value is 0; what remains is rounding of derivative and lift
+    # sums, of size eps * (operator scale) * |q|, the operator scale taken as
+    # |L x| / |x| for a random state x
+    x = torch.randn_like(q)
+    op_scale = float(c.rhs(0.0, x).abs().max() / x.abs().max())
+    scale = float(q.abs().max())
+    eps = 2.2e-16 if prec == 64 else 1.2e-7
+    _report("steady", prec=prec, max_rhs=float(r.abs().max()), scale=scale, op_scale=op_scale)
+    assert float(r.abs().max()) <= 1000 * eps * op_scale * scale
+
+
+def test_zero_steps_and_error_paths():
+    torch = _torch()
+    import paper_1711_01175_amd as P
+    from workloads import media
+    from workloads.mesh import kuhn_periodic_mesh
+    EToV, VXYZ = kuhn_periodic_mesh(3)
+    c = P.Context(3, 32)
+    c.set_mesh(EToV, VXYZ)
+    c.bind_workspace(max_receivers=1, max_record_steps=2)
+    c.set_material(*media.smooth(c.quadrature_points()))
+    q0 = torch.randn((c.K, 9, c.Np), dtype=torch.float32, device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(3))
+    c.set_state(q0, 0.25)
+    dt = c.cfl_dt(0.5)
+    c.step(dt, 0)
+    assert torch.equal(c.get_state(), q0) and c.time() == 0.25
+    for bad in ((0.0, 1), (-dt, 1), (dt, -1)):
+        with pytest.raises(P.EwdgError) as e:
+            c.step(*bad)
+        assert e.value.code == P.ewdg.EWDG_EINVAL
+    with pytest.raises(P.EwdgError) as e:
+        c.set_receivers(np.zeros((2, 3)))                  # more than the workspace holds
+    assert e.value.code == P.ewdg.EWDG_ENOMEM
+    with pytest.raises(P.EwdgError) as e:
+        c.set_receivers(np.array([[3.0, 0.0, 0.0]]))       # outside the cube
+    assert e.value.code == P.ewdg.EWDG_EPOINT
+    c.set_receivers(np.array([[0.1, 0.2, 0.3]]))
+    c.step(dt, 2)
+    with pytest.raises(P.EwdgError) as e:
+        c.step(dt, 1)                                      # record capacity exhausted
+    assert e.value.code == P.ewdg.EWDG_ENOMEM
+    assert c.receivers().shape == (2, 1, 3)

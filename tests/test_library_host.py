@@ -150,3 +150,34 @@ def test_cfl_dt_needs_material():
     with pytest.raises(B.EwdgError) as e:
         c.cfl_dt(0.5)
     assert e.value.code == B.EWDG_ESTATE
+
+
+def test_empty_and_oversized_meshes_are_rejected():
+    """K = 0 and K >= 2^26 (the connectivity packs neighbour * 32 into int32)
+    are refused before any array is read."""
+    import ctypes
+    lib = B.load()
+    c = P.Context(2, 32)
+    one = np.zeros((1, 4), dtype=np.int64)
+    xyz = np.zeros((1, 4, 3))
+    for K in (0, -1, 1 << 26):
+        rc = lib.ewdg_set_mesh(c.h, ctypes.c_int64(K), one.ctypes.data_as(ctypes.c_void_p),
+                               xyz.ctypes.data_as(ctypes.c_void_p))
+        assert rc == B.EWDG_EINVAL, (K, rc)
+
+
+def test_empty_batch_and_null_arguments():
+    import ctypes
+    lib = B.load()
+    size = ctypes.c_size_t()
+    assert lib.ewdg_batch_table_bytes(0, ctypes.byref(size)) == B.EWDG_OK and size.value > 0
+    assert lib.ewdg_batch_table_bytes(-1, ctypes.byref(size)) == B.EWDG_EINVAL
+    assert lib.ewdg_step_batch(None, 0, None, 5, None, 0, None) == B.EWDG_OK
+    assert lib.ewdg_step_batch(None, 2, None, 5, None, 0, None) == B.EWDG_EINVAL
+    assert lib.ewdg_create(4, 32, None, None) == B.EWDG_EINVAL
+    c = P.Context(3, 64)
+    assert lib.ewdg_workspace_bytes(c.h, 0, 0, ctypes.byref(size)) == B.EWDG_ESTATE   # no mesh yet
+    EToV, VXYZ = kuhn_periodic_mesh(3)
+    c.set_mesh(EToV, VXYZ)
+    assert lib.ewdg_workspace_bytes(c.h, -1, 0, ctypes.byref(size)) == B.EWDG_EINVAL
+    assert lib.ewdg_adjoint_workspace_bytes(c.h, 10, 5, ctypes.byref(size)) == B.EWDG_ESTATE  # not bound
