@@ -186,9 +186,11 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
  *
  * ewdg_adjoint_workspace_bytes: size of a second caller-owned workspace for
  * at most max_steps recorded steps with a checkpoint of (q, sigma_h) every
- * checkpoint_every steps; it holds ceil(max_steps/checkpoint_every)
- * checkpoints plus checkpoint_every step-start states of one segment, about
- * (ceil(max_steps/C) + C + 11) * 15 K Np values in the run precision.  Call
+ * checkpoint_every = C steps; it holds ceil(max_steps/C) checkpoints and,
+ * for the segment being reversed, the inputs of all 5 C stages with their
+ * velocity right-hand sides: about (ceil(max_steps/C) + 6 C + 6) * 15 K Np
+ * values in the run precision (memory is traded for recomputation: a
+ * smaller C needs less).  Call
  * after ewdg_bind_workspace (the receiver capacity is taken from it);
  * binding the forward workspace again or a new mesh drops the binding. */
 int ewdg_adjoint_workspace_bytes(const ewdg_ctx* ctx, int max_steps, int checkpoint_every, size_t* bytes);

@@ -17,18 +17,16 @@ struct AdjDev {
   void* qbar = nullptr;      // [K][9][Np] adjoint of the state
   void* rbar = nullptr;      // [K][9][Np] adjoint of the LSRK register
   void* rhs = nullptr;       // [K][9][Np] L q + f (single right-hand-side adjoint)
-  void* rhsv = nullptr;      // [5][K][3][Np] velocity rows of L q_i + f_i of one step
+  void* rhsv = nullptr;      // [5 C][K][3][Np] velocity rows of L q_i + f_i of one segment
   void* res = nullptr;       // [K][9][Np] LSRK register of the recomputation
   double* g = nullptr;       // [K][3] parameter gradient
   double* resid = nullptr;   // [nsteps][nr][3] receiver residuals
-  // snapshots of (q, sigma_h(q)): checkpoints, step starts of one segment and
-  // the stage inputs of one step
+  // snapshots of (q, sigma_h(q)): checkpoints, and the stage inputs of every
+  // stage of every step of one segment
   void* ck_q = nullptr;      // [nck][K][9][Np]
   void* ck_s = nullptr;      // [nck][K][6][Np]
-  void* seg_q = nullptr;     // [C][K][9][Np]
-  void* seg_s = nullptr;     // [C][K][6][Np]
-  void* st_q = nullptr;      // [5][K][9][Np] (q_1..q_5 of one step)
-  void* st_s = nullptr;      // [5][K][6][Np]
+  void* st_q = nullptr;      // [5 C + 1][K][9][Np]
+  void* st_s = nullptr;      // [5 C + 1][K][6][Np]
 };
 
 // qbar += scale * L^T y; if q is given also g += scale * y . d(L q + f)/d theta

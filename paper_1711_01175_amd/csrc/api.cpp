@@ -779,16 +779,17 @@ size_t adj_layout(const ewdg_ctx* c, int max_steps, int every, int max_rec, char
   a.qbar = take(9 * Np * K * ts);
   a.rbar = take(9 * Np * K * ts);
   a.rhs = take(9 * Np * K * ts);
-  a.rhsv = take(5 * 3 * Np * K * ts);
+  a.rhsv = take(static_cast<size_t>(every) * 5 * 3 * Np * K * ts);
   a.res = take(9 * Np * K * ts);
   a.g = reinterpret_cast<double*>(take(3 * K * 8));
   a.resid = reinterpret_cast<double*>(take(static_cast<size_t>(max_steps) * (max_rec > 0 ? max_rec : 1) * 3 * 8));
   a.ck_q = take(nck * 9 * Np * K * ts);
   a.ck_s = take(nck * 6 * Np * K * ts);
-  a.seg_q = take(static_cast<size_t>(every) * 9 * Np * K * ts);
-  a.seg_s = take(static_cast<size_t>(every) * 6 * Np * K * ts);
-  a.st_q = take(5 * 9 * Np * K * ts);
-  a.st_s = take(5 * 6 * Np * K * ts);
+  // stage inputs (q_i, sigma_h(q_i)) of every stage of every step of one
+  // segment, plus one slot for the last stage output
+  const size_t nst = static_cast<size_t>(every) * 5 + 1;
+  a.st_q = take(nst * 9 * Np * K * ts);
+  a.st_s = take(nst * 6 * Np * K * ts);
   if (ad) *ad = a;
   return off;
 }
@@ -925,48 +926,34 @@ int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
   const int nseg = (NS + C - 1) / C;
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * C, len = std::min(C, NS - s0);
-    // step-start states of the segment, recomputed from its checkpoint
-    if ((rc = copy_dev(c, a.seg_q, slot(a.ck_q, c, 9, seg), 9))) return rc;
-    if ((rc = copy_dev(c, a.seg_s, slot(a.ck_s, c, 6, seg), 6))) return rc;
-    for (int m = 0; m + 1 < len; ++m) {
+    // every stage input of the segment and the velocity rows of every stage
+    // right-hand side, recomputed from the segment's checkpoint; slot 5 m + i
+    // holds the input of stage i of step m
+    if ((rc = copy_dev(c, slot(a.st_q, c, 9, 0), slot(a.ck_q, c, 9, seg), 9))) return rc;
+    if ((rc = copy_dev(c, slot(a.st_s, c, 6, 0), slot(a.ck_s, c, 6, seg), 6))) return rc;
+    for (int m = 0; m < len; ++m) {
       const double tn = c->step_t[s0 + m];
-      const void* qi = slot(a.seg_q, c, 9, m);
-      const void* si = slot(a.seg_s, c, 6, m);
       for (int i = 0; i < 5; ++i) {
-        void* qo = i < 4 ? slot(a.st_q, c, 9, i) : slot(a.seg_q, c, 9, m + 1);
-        void* so = i < 4 ? slot(a.st_s, c, 6, i) : slot(a.seg_s, c, 6, m + 1);
-        if ((rc = stage_on(c, i, dt, tn, qi, si, qo, so))) return rc;
-        qi = qo;
-        si = so;
+        const size_t k = 5 * static_cast<size_t>(m) + i;
+        if ((rc = stage_on(c, i, dt, tn, slot(a.st_q, c, 9, k), slot(a.st_s, c, 6, k), slot(a.st_q, c, 9, k + 1),
+                           slot(a.st_s, c, 6, k + 1), slot(a.rhsv, c, 3, k))))
+          return rc;
       }
     }
     for (int m = len - 1; m >= 0; --m) {
       const int n = s0 + m;
-      const double tn = c->step_t[n];
       // misfit term of the state after step n
       if (c->nr > 0) {
         if ((rc = c->hip(launch_adj_receivers(c->d, a.qbar, a.resid + static_cast<size_t>(n) * c->nr * 3, c->nr, dt,
                                               c->stream), "adjoint receivers")))
           return rc;
       }
-      // stage inputs q_1..q_4 of step n and the velocity rows of every
-      // stage's right-hand side (the fifth stage's output is not needed)
-      const void* qi = slot(a.seg_q, c, 9, m);
-      const void* si = slot(a.seg_s, c, 6, m);
-      for (int i = 0; i < 5; ++i) {
-        if ((rc = stage_on(c, i, dt, tn, qi, si, slot(a.st_q, c, 9, i), slot(a.st_s, c, 6, i),
-                           slot(a.rhsv, c, 3, i))))
-          return rc;
-        qi = slot(a.st_q, c, 9, i);
-        si = slot(a.st_s, c, 6, i);
-      }
       for (int i = 4; i >= 0; --i) {
-        const void* qin = i == 0 ? slot(a.seg_q, c, 9, m) : slot(a.st_q, c, 9, i - 1);
-        const void* sin = i == 0 ? slot(a.seg_s, c, 6, m) : slot(a.st_s, c, 6, i - 1);
+        const size_t k = 5 * static_cast<size_t>(m) + i;
         if ((rc = c->hip(launch_axpy(c->prec, a.rbar, a.qbar, kRkB[i], static_cast<int64_t>(n9), c->stream), "axpy")))
           return rc;
-        if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, qin, sin, slot(a.rhsv, c, 3, i), 3 * c->re.Np, a.qbar,
-                                        a.g, dt, c->stream),
+        if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, slot(a.st_q, c, 9, k), slot(a.st_s, c, 6, k),
+                                        slot(a.rhsv, c, 3, k), 3 * c->re.Np, a.qbar, a.g, dt, c->stream),
                          "adjoint")))
           return rc;
         if ((rc = c->hip(launch_scal(c->prec, a.rbar, kRkA[i], static_cast<int64_t>(n9), c->stream), "scal")))
