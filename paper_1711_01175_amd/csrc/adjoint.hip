@@ -15,6 +15,22 @@
 #include "dev.hpp"
 #include "kcommon.hpp"
 
+// Tuning constants (measured on MI355X at N=4): EWDG_ADJ_LDS caps the LDS of
+// one workgroup in KiB (fewer elements per workgroup, more workgroups per
+// CU); EWDG_ADJ_UNROLL > 0 forces that unroll factor on the inner loops.
+#ifndef EWDG_ADJ_LDS
+#define EWDG_ADJ_LDS 20
+#endif
+#ifndef EWDG_ADJ_UNROLL
+#define EWDG_ADJ_UNROLL 0
+#endif
+#define EWDG_PRAGMA(x) _Pragma(#x)
+#if EWDG_ADJ_UNROLL > 0
+#define EWDG_UNROLL_N(n) EWDG_PRAGMA(unroll n)
+#else
+#define EWDG_UNROLL_N(n)
+#endif
+
 namespace ewdg {
 
 template <typename T>
@@ -54,7 +70,7 @@ struct AdjCfg {
   static constexpr int per_a = 12 * S::Np + 32;
   static constexpr int per_b = 27 * S::Np + 6 * S::Nq + 8 * S::Nfp + 2 * S::Nq + S::Np + 32;
   static constexpr int per = per_a > per_b ? per_a : per_b;
-  static constexpr int e_lds = (60 * 1024) / (per * static_cast<int>(sizeof(T)));
+  static constexpr int e_lds = (EWDG_ADJ_LDS * 1024) / (per * static_cast<int>(sizeof(T)));
   static constexpr int e_thr = 256 / S::Np > 0 ? 256 / S::Np : 1;
   static constexpr int E = (e_lds < e_thr ? e_lds : e_thr) > 0 ? (e_lds < e_thr ? e_lds : e_thr) : 1;
   static constexpr int NT = ((E * S::Np + 63) / 64) * 64 > 64 ? ((E * S::Np + 63) / 64) * 64 : 64;
@@ -97,6 +113,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjA(AdjArgs<T> a) {
     const int e = x / Np, i = x % Np;
     const T* Wr = a.W + (e0 + e) * Np * Np + i * Np;   // W_ji over j
     T o[3] = {0, 0, 0};
+    EWDG_UNROLL_N(EWDG_ADJ_UNROLL)
     for (int j = 0; j < Np; ++j) {
       const T wv = Wr[j];
 #pragma unroll
@@ -121,6 +138,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjA(AdjArgs<T> a) {
     T D[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) D[c] = 0;
+    EWDG_UNROLL_N(EWDG_ADJ_UNROLL)
     for (int i = 0; i < Np; ++i) {
       const T L = a.LIFT[i * NF + fj];
 #pragma unroll
@@ -241,6 +259,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int k = 0; k < 3; ++k) Gb[c][k] = 0;
+    EWDG_UNROLL_N(EWDG_ADJ_UNROLL)
     for (int r = 0; r < Np; ++r) {
       T dk[3];
 #pragma unroll
@@ -317,6 +336,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
   for (int x = tid; x < ne * Nq; x += NT) {
     const int e = x / Nq, qp = x % Nq;
     T tau[6] = {0, 0, 0, 0, 0, 0};
+    EWDG_UNROLL_N(EWDG_ADJ_UNROLL)
     for (int i = 0; i < Np; ++i) {
       const T p = a.Pq[i * Nq + qp];
 #pragma unroll
@@ -328,6 +348,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
     for (int m = 0; m < 6; ++m) Qd[(e * 6 + m) * Nq + qp] = T(2) * mu * tau[m] + (m < 3 ? lam * trt : T(0));
     if (a.q) {
       T ep[6] = {0, 0, 0, 0, 0, 0};
+      EWDG_UNROLL_N(EWDG_ADJ_UNROLL)
       for (int j = 0; j < Np; ++j) {
         const T v = a.VqT[j * Nq + qp];
 #pragma unroll
@@ -345,6 +366,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
   for (int x = tid; x < ne * Np; x += NT) {
     const int e = x / Np, j = x % Np;
     T eb[6] = {0, 0, 0, 0, 0, 0};
+    EWDG_UNROLL_N(EWDG_ADJ_UNROLL)
     for (int qp = 0; qp < Nq; ++qp) {
       const T v = a.Vq[qp * Np + j];
 #pragma unroll
@@ -369,6 +391,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
   for (int e = tid; e < ne; e += NT) {
     double gr = 0, gl = 0, gm = 0, zp = 0, zs = 0;
     for (int j = 0; j < Np; ++j) gr += static_cast<double>(pr[e * Np + j]);
+    EWDG_UNROLL_N(EWDG_ADJ_UNROLL)
     for (int qp = 0; qp < Nq; ++qp) {
       gl += static_cast<double>(pp[(e * Nq + qp) * 2]);
       gm += static_cast<double>(pp[(e * Nq + qp) * 2 + 1]);
