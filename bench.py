@@ -24,11 +24,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_stage_cube32_N4.md")
-KERNEL_SOURCES = ("kernels.hip", "kcommon.hpp", "dev.hpp")
+KERNEL_SOURCES = ("kernels.hip", "kcommon.hpp", "dev.hpp", "tiles.hpp")
 
 
 def kernel_source_digest():
-    """sha256 over the stage kernel's sources, to tell whether the committed
+    """sha256 over the stage kernel's sources (kernels.hip, kcommon.hpp, dev.hpp,
+    tiles.hpp), to tell whether the committed
     counter profile was taken on the kernel that runs now."""
     import hashlib
     h = hashlib.sha256()

@@ -14,6 +14,7 @@
 #include "adjdev.hpp"
 #include "dev.hpp"
 #include "kcommon.hpp"
+#include "tiles.hpp"
 
 // Tuning constants (measured on MI355X at N=4): EWDG_ADJ_LDS caps the LDS of
 // one workgroup in KiB (fewer elements per workgroup, more workgroups per
@@ -23,6 +24,12 @@
 #endif
 #ifndef EWDG_ADJ_UNROLL
 #define EWDG_ADJ_UNROLL 0
+#endif
+#ifndef EWDG_ADJ_MMA
+#define EWDG_ADJ_MMA 1
+#endif
+#ifndef EWDG_ADJ_OCC
+#define EWDG_ADJ_OCC 2
 #endif
 #define EWDG_PRAGMA(x) _Pragma(#x)
 #if EWDG_ADJ_UNROLL > 0
@@ -60,6 +67,11 @@ struct AdjArgs {
   const T* Vq;         // [Nq][Np]
   const T* VqT;        // [Np][Nq]
   const T* Pq;         // [Np][Nq]
+  // fragment-order operators for the matrix-core pass B
+  const T* DTpad;      // D_k^T  [3][RT][NpK/4][64]
+  const T* PqTpad;     // Pq^T   [QT][NpK/4][64]
+  const T* VqTpad;     // Vq^T   [RT][NqK/4][64]
+  const T* Vqpad;      // Vq     [QT][NpK/4][64]
   int64_t K;
   T scale;
 };
@@ -413,6 +425,361 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
   }
 }
 
+// Pass B on the matrix cores, for a tile of 16 elements (matrix columns are
+// (field, element) pairs as in the stage kernel; the owner wave of node row
+// tile R accumulates rows 16R..16R+15):
+//  1. Gb_c^k = D_k^T ytil_c and vbar_c = sum_k D_k^T z_c^k, with z_c^k the
+//     strain adjoint contracted with dr_k/dx; sigma-bar folds Gb with dr/dx;
+//  2. face sensitivities from both sides are added at the face nodes;
+//  3. tau = Pq^T sigma-bar at the quadrature points, the elasticity adjoint
+//     2 mu tau + lambda tr(tau) I, and (for the gradient) eps_q = Vq eps;
+//  4. epsbar = Vq^T (2 mu tau + lambda tr(tau) I), chunk by chunk;
+//  5. qbar += scale (vbar, epsbar); per-element gradient in a fixed order.
+template <typename T, int N>
+struct AdjTile {
+  using TL = Tile<N>;
+  static constexpr int Np = TL::Np, Nfp = TL::Nfp, NpK = TL::NpK, E = TL::E, NW = TL::NW;
+  static constexpr int SV = TL::SV, SE = TL::SE, SQ = TL::SQ, QC = TL::QC;
+  static constexpr int SB = 9 * 16 + 1;                       // sigma-bar (0..5) | v-bar (6..8)
+  static constexpr int R1 = cmax2(2 * NpK * SV, NpK * SE);    // volume operands, own strains, epsbar
+  static constexpr int R2 = NpK * SB;
+  static constexpr int R3 = cmax2(cmax2(E * 4 * Nfp * 2, QC * SQ), E * Np);   // zf, then Qd, then rho partials
+  static constexpr int RED = NW * 64 * 2;
+  static constexpr int BYTES = (R1 + R2 + R3 + RED + E * 32) * static_cast<int>(sizeof(T)) + E * 2 * 8;
+  static constexpr bool fits = BYTES <= 156 * 1024;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__((Tile<N>::NT), EWDG_ADJ_OCC) void k_adjB_mma(AdjArgs<T> a) {
+  using TL = Tile<N>;
+  using AT = AdjTile<T, N>;
+  using M = Mfma<T>;
+  using acc_t = typename M::acc_t;
+  constexpr int Np = TL::Np, Nfp = TL::Nfp, Nq = TL::Nq, NqP = TL::NqP, E = TL::E;
+  constexpr int NpK = TL::NpK, NqK = TL::NqK, RT = TL::RT, QT = TL::QT, NW = TL::NW, NT = TL::NT;
+  constexpr int SV = AT::SV, SE = AT::SE, SQ = AT::SQ, QC = AT::QC, SB = AT::SB;
+  constexpr int KD = NpK / 4, KQ = QC / 4, NQC = (QT * 16 + QC - 1) / QC;
+  __shared__ T r1[AT::R1];
+  __shared__ T r2[AT::R2];
+  __shared__ T r3[AT::R3];
+  __shared__ T red[AT::RED];
+  __shared__ T sgeo[E * 32];
+  __shared__ double zsum[E * 2];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, lr = l & 15, lg = l >> 4;
+  const bool own = w < RT;
+  const int R = w;
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * E;
+  const int ne = static_cast<int>((a.K - e0) < E ? (a.K - e0) : E);
+  const bool grad = a.q && a.g;
+
+  for (int x = tid; x < E * 27; x += NT) {
+    const int e = x / 27, m = x % 27;
+    T v = T(0);
+    if (e < ne) {
+      if (m < 9) v = a.geo[(e0 + e) * 9 + m];
+      else if (m < 25) v = a.fgeo[(e0 + e) * 16 + (m - 9)];
+      else v = a.Z[(e0 + e) * 2 + (m - 25)];
+    }
+    sgeo[e * 32 + m] = v;
+  }
+  T* Sv = r1;               // [NpK][SV] ytil_c at column c*16+e
+  T* SG = r1 + NpK * SV;    // [NpK][SV] z_c^k for the current direction
+  for (int x = tid; x < E * 3 * NpK; x += NT) {
+    const int e = x / (3 * NpK), rem = x % (3 * NpK), c = rem / NpK, j = rem % NpK;
+    T v = T(0);
+    if (e < ne && j < Np) v = a.ytil[(e0 + e) * 3 * Np + c * Np + j];
+    Sv[j * SV + c * 16 + e] = v;
+    if (j >= Np) SG[j * SV + c * 16 + e] = T(0);
+  }
+  __syncthreads();
+
+  // ---- 1. transposed volume terms
+  acc_t sb[6], vb[3];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) sb[m] = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vb[c] = acc_t{0, 0, 0, 0};
+  constexpr int NPT = (E * Np + NT - 1) / NT;
+  // this thread's strain adjoints, loaded once for the three directions
+  T yr[NPT][6];
+#pragma unroll
+  for (int p = 0; p < NPT; ++p) {
+    const int x = tid + p * NT;
+    const int e = x / Np, r = x % Np;
+    const bool ok = x < E * Np && e < ne;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) yr[p][m] = ok ? a.y[(e0 + e) * 9 * Np + (3 + m) * Np + r] : T(0);
+  }
+#pragma unroll 1
+  for (int k = 0; k < 3; ++k) {
+    T af[KD];
+    if (own) {
+      const T* D = a.DTpad + ((k * RT + R) * KD) * 64 + l;
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) af[kk] = D[kk * 64];
+    }
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+      const int x = tid + p * NT;
+      if (x < E * Np) {
+        const int e = x / Np, r = x % Np;
+        const T* y6 = yr[p];
+        const T* g = &sgeo[e * 32 + k * 3];
+        // z_c = sum_m g_m ybar_cm, ybar the strain adjoint as a tensor (off-diagonal halves)
+        SG[r * SV + 0 * 16 + e] = g[0] * y6[0] + T(0.5) * (g[1] * y6[5] + g[2] * y6[4]);
+        SG[r * SV + 1 * 16 + e] = g[1] * y6[1] + T(0.5) * (g[0] * y6[5] + g[2] * y6[3]);
+        SG[r * SV + 2 * 16 + e] = g[2] * y6[2] + T(0.5) * (g[0] * y6[4] + g[1] * y6[3]);
+      }
+    }
+    __syncthreads();
+    if (own) {
+      acc_t gb[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gb[c] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) {
+        const int row = (4 * kk + lg) * SV + lr;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          gb[c] = M::mma(af[kk], Sv[row + c * 16], gb[c]);
+          vb[c] = M::mma(af[kk], SG[row + c * 16], vb[c]);
+        }
+      }
+      const T g0 = sgeo[lr * 32 + k * 3], g1 = sgeo[lr * 32 + k * 3 + 1], g2 = sgeo[lr * 32 + k * 3 + 2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sb[0][r] += g0 * gb[0][r];
+        sb[1][r] += g1 * gb[1][r];
+        sb[2][r] += g2 * gb[2][r];
+        sb[3][r] += g2 * gb[1][r] + g1 * gb[2][r];
+        sb[4][r] += g2 * gb[0][r] + g0 * gb[2][r];
+        sb[5][r] += g1 * gb[0][r] + g0 * gb[1][r];
+      }
+    }
+    __syncthreads();
+  }
+  T* SBV = r2;   // [NpK][SB]
+  if (own) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = R * 16 + M::row(lg, r);
+      if (i < NpK) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) SBV[i * SB + m * 16 + lr] = sb[m][r];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) SBV[i * SB + (6 + c) * 16 + lr] = vb[c][r];
+      }
+    }
+  }
+  // own strains of the forward state (gradient), B operand of eps_q = Vq eps
+  T* Sown = r1;  // [NpK][SE]
+  if (grad) {
+    for (int x = tid; x < E * 6 * NpK; x += NT) {
+      const int e = x / (6 * NpK), rem = x % (6 * NpK), m = rem / NpK, j = rem % NpK;
+      Sown[j * SE + m * 16 + e] = (e < ne && j < Np) ? a.q[(e0 + e) * 9 * Np + (3 + m) * Np + j] : T(0);
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. face sensitivities of both sides, face by face
+  T* zf = r3;    // [E][4][Nfp][2]
+  constexpr int FPT = (E * Nfp + NT - 1) / NT;
+  // own and neighbour-side sensitivities of all four faces, loads issued together
+  T fsum[FPT][4][8];
+#pragma unroll
+  for (int p = 0; p < FPT; ++p) {
+    const int x = tid + p * NT;
+    const int e = x / Nfp, j = x % Nfp;
+    const bool ok = x < E * Nfp && e < ne;
+    const int ee = ok ? e : 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int32_t wd = ok ? a.conn[(e0 + ee) * 4 + f] : static_cast<int32_t>((e0 * 4) << 5);
+      const int64_t nb = wd >> 5;
+      const int code = wd & 31;
+      const int jn = a.nbrface[((f * 4 + code / 6) * 6 + code % 6) * Nfp + (ok ? j : 0)];
+      const T* fo = a.fown + (((e0 + ee) * 4 + f) * Nfp + (ok ? j : 0)) * 8;
+      const T* fn = a.fnbr + ((nb * 4 + code / 6) * Nfp + jn) * 8;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fsum[p][f][c] = fo[c] + fn[c];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fsum[p][f][3 + c] = fo[3 + c] - fn[3 + c];
+      fsum[p][f][6] = fo[6] + fn[6];
+      fsum[p][f][7] = fo[7] + fn[7];
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+#pragma unroll
+    for (int p = 0; p < FPT; ++p) {
+      const int x = tid + p * NT;
+      const int e = x / Nfp, j = x % Nfp;
+      if (x >= E * Nfp || e >= ne) continue;
+      const int il = a.fmask[f * Nfp + j];
+      const T* gg = &sgeo[e * 32];
+      const T n[3] = {gg[9 + f * 4], gg[9 + f * 4 + 1], gg[9 + f * 4 + 2]};
+      const T* fs = fsum[p][f];
+      T* row = &SBV[il * SB + e];
+      const T* Te = fs + 3;   // own traction sensitivity minus the neighbour's (its normal is -n)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) row[(6 + c) * 16] += fs[c];
+      row[0 * 16] += Te[0] * n[0];
+      row[1 * 16] += Te[1] * n[1];
+      row[2 * 16] += Te[2] * n[2];
+      row[3 * 16] += Te[1] * n[2] + Te[2] * n[1];
+      row[4 * 16] += Te[0] * n[2] + Te[2] * n[0];
+      row[5 * 16] += Te[0] * n[1] + Te[1] * n[0];
+      zf[(e * 4 * Nfp + f * Nfp + j) * 2] = fs[6];
+      zf[(e * 4 * Nfp + f * Nfp + j) * 2 + 1] = fs[7];
+    }
+    __syncthreads();
+  }
+  if (grad) {
+    for (int e = tid; e < ne; e += NT) {
+      double zp = 0, zs = 0;
+      for (int x = 0; x < 4 * Nfp; ++x) {
+        zp += static_cast<double>(zf[(e * 4 * Nfp + x) * 2]);
+        zs += static_cast<double>(zf[(e * 4 * Nfp + x) * 2 + 1]);
+      }
+      zsum[e * 2] = zp;
+      zsum[e * 2 + 1] = zs;
+    }
+  }
+  __syncthreads();
+
+  // ---- 3./4. transposed projection, chunk by chunk
+  T* Qd = r3;    // [QC][SQ]
+  acc_t eb[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) eb[m] = acc_t{0, 0, 0, 0};
+  T gl_acc = 0, gm_acc = 0;
+  const int ec = lr < ne ? lr : ne - 1;
+#pragma unroll 1
+  for (int qc = 0; qc < NQC; ++qc) {
+    const int q0 = qc * QC;
+    const int rows = (NqK - q0) < QC ? (NqK - q0) : QC;
+#pragma unroll 1
+    for (int Rq = q0 / 16 + w; Rq < QT && Rq * 16 < q0 + QC; Rq += NW) {
+      T pf[KD];
+      const T* Pr = a.PqTpad + (Rq * KD) * 64 + l;
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) pf[kk] = Pr[kk * 64];
+      acc_t tau[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) tau[m] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) {
+        const int row = (4 * kk + lg) * SB + lr;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) tau[m] = M::mma(pf[kk], SBV[row + m * 16], tau[m]);
+      }
+      acc_t ep[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) ep[m] = acc_t{0, 0, 0, 0};
+      if (grad) {
+        T vf[KD];
+        const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
+#pragma unroll
+        for (int kk = 0; kk < KD; ++kk) vf[kk] = Vr[kk * 64];
+#pragma unroll
+        for (int kk = 0; kk < KD; ++kk) {
+          const int row = (4 * kk + lg) * SE + lr;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) ep[m] = M::mma(vf[kk], Sown[row + m * 16], ep[m]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = Rq * 16 + M::row(lg, r);
+        if (q >= NqK) continue;
+        const bool ok = q < Nq && lr < ne;
+        const int qq = q < Nq ? q : Nq - 1;
+        const T lam = ok ? a.lm[(e0 + ec) * 2 * NqP + qq] : T(0);
+        const T mu = ok ? a.lm[(e0 + ec) * 2 * NqP + NqP + qq] : T(0);
+        const T trt = tau[0][r] + tau[1][r] + tau[2][r];
+        T* o = &Qd[(q - q0) * SQ + lr];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) o[m * 16] = T(2) * mu * tau[m][r] + (m < 3 ? lam * trt : T(0));
+        if (grad) {
+          const T tr = ep[0][r] + ep[1][r] + ep[2][r];
+          T pm = 0;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) pm += tau[m][r] * ep[m][r];
+          gl_acc += lam * tr * trt;
+          gm_acc += T(2) * mu * pm;
+        }
+      }
+    }
+    __syncthreads();
+    if (own) {
+      const T* Vt = a.VqTpad + (R * (NqK / 4) + q0 / 4) * 64 + l;
+#pragma unroll
+      for (int u = 0; u < KQ; ++u) {
+        if (4 * u < rows) {
+          const T vt = Vt[u * 64];
+          const int row = (4 * u + lg) * SQ + lr;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) eb[m] = M::mma(vt, Qd[row + m * 16], eb[m]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- 5. outputs
+  T* Seb = r1;   // [NpK][SE] epsbar (the own strains are no longer needed)
+  if (own) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = R * 16 + M::row(lg, r);
+      if (i < Np) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) Seb[i * SE + m * 16 + lr] = eb[m][r];
+      }
+    }
+  }
+  red[(w * 64 + l) * 2] = gl_acc;
+  red[(w * 64 + l) * 2 + 1] = gm_acc;
+  __syncthreads();
+  for (int x = tid; x < ne * 9 * Np; x += NT) {
+    const int e = x / (9 * Np), c = (x / Np) % 9, j = x % Np;
+    const T v = (c < 3) ? SBV[j * SB + (6 + c) * 16 + e] : Seb[j * SE + (c - 3) * 16 + e];
+    a.qbar[e0 * 9 * Np + x] += a.scale * v;
+  }
+  if (!grad) return;
+  T* pr = r3;    // [E][Np] density partials (the chunk buffer is free)
+  for (int x = tid; x < ne * Np; x += NT) {
+    const int e = x / Np, j = x % Np;
+    T p = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      p += a.y[(e0 + e) * 9 * Np + c * Np + j] * a.rhs[(e0 + e) * a.rhs_es + c * Np + j];
+    pr[e * Np + j] = -p;
+  }
+  __syncthreads();
+  for (int e = tid; e < ne; e += NT) {
+    double gr = 0, gl = 0, gm = 0;
+    for (int j = 0; j < Np; ++j) gr += static_cast<double>(pr[e * Np + j]);
+    for (int ww = 0; ww < NW; ++ww)
+      for (int g4 = 0; g4 < 4; ++g4) {
+        gl += static_cast<double>(red[(ww * 64 + g4 * 16 + e) * 2]);
+        gm += static_cast<double>(red[(ww * 64 + g4 * 16 + e) * 2 + 1]);
+      }
+    const double zp = zsum[e * 2], zs = zsum[e * 2 + 1];
+    // chain rule through Z_p = sqrt(rho (lambda + 2 mu)), Z_s = sqrt(rho mu)
+    const double* mn = a.means + (e0 + e) * 3;
+    const double Zp = sqrt(mn[0] * (mn[1] + 2.0 * mn[2])), Zs = sqrt(mn[0] * mn[2]);
+    gr += 0.5 * Zp * zp + 0.5 * Zs * zs;
+    gl += mn[0] * mn[1] / (2.0 * Zp) * zp;
+    gm += mn[0] * mn[2] / Zp * zp + 0.5 * Zs * zs;
+    const double sc = static_cast<double>(a.scale);
+    a.g[(e0 + e) * 3 + 0] += sc * gr;
+    a.g[(e0 + e) * 3 + 1] += sc * gl;
+    a.g[(e0 + e) * 3 + 2] += sc * gm;
+  }
+}
+
 // qbar_v(receiver element) += scale * l(x_r) resid_r, receivers in order.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_adj_receivers(T* qbar, const double* rows, const int32_t* elem,
@@ -469,6 +836,10 @@ static AdjArgs<T> adj_args(const Dev& d, const AdjDev& ad, const void* y, const 
   a.Vq = static_cast<const T*>(d.Vqr);
   a.VqT = static_cast<const T*>(d.VqT);
   a.Pq = static_cast<const T*>(d.Pqr);
+  a.DTpad = static_cast<const T*>(d.DTpad);
+  a.PqTpad = static_cast<const T*>(d.PqTpad);
+  a.VqTpad = static_cast<const T*>(d.VqTpad);
+  a.Vqpad = static_cast<const T*>(d.Vqpad);
   a.K = d.K;
   a.scale = static_cast<T>(scale);
   return a;
@@ -484,7 +855,12 @@ static hipError_t adjoint_impl(const Dev& d, const AdjDev& ad, const void* y, co
   hipLaunchKernelGGL((k_adjA<T, N>), dim3(grid), dim3(C::NT), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_adjB<T, N>), dim3(grid), dim3(C::NT), 0, st, a);
+  if constexpr (AdjTile<T, N>::fits && EWDG_ADJ_MMA) {
+    const unsigned gridm = static_cast<unsigned>((d.K + Tile<N>::E - 1) / Tile<N>::E);
+    hipLaunchKernelGGL((k_adjB_mma<T, N>), dim3(gridm), dim3(Tile<N>::NT), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_adjB<T, N>), dim3(grid), dim3(C::NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -119,6 +119,9 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.Lpad = take(4 * (NpR / 16) * (NfpK / 4) * 64 * ts);
   d.Vqpad = take((NqR / 16) * (NpK / 4) * 64 * ts);
   d.Pqpad = take((NpR / 16) * (NqK / 4) * 64 * ts);
+  d.DTpad = take(3 * (NpR / 16) * (NpK / 4) * 64 * ts);
+  d.PqTpad = take((NqR / 16) * (NpK / 4) * 64 * ts);
+  d.VqTpad = take((NpR / 16) * (NqK / 4) * 64 * ts);
   d.VqT = take(Nq * Np * ts);
   d.PqT = take(Nq * Np * ts);
   d.Dk = take(3 * Np * Np * ts);
@@ -394,6 +397,16 @@ int ewdg_bind_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_receivers,
     if ((rc = upload_run(c, c->d.Lpad, Lp))) return rc;
     if ((rc = upload_run(c, c->d.Vqpad, Vp))) return rc;
     if ((rc = upload_run(c, c->d.Pqpad, Pp))) return rc;
+    // transposed operators for the adjoint kernels
+    std::vector<double> DTp(3 * RT * KD * 64), PTp(QT * KD * 64), VTp(RT * KQ * 64);
+    frag(transpose(re.Dr, Np, Np), Np, Np, RT, KD, DTp, 0);
+    frag(transpose(re.Ds, Np, Np), Np, Np, RT, KD, DTp, static_cast<size_t>(RT) * KD * 64);
+    frag(transpose(re.Dt, Np, Np), Np, Np, RT, KD, DTp, 2 * static_cast<size_t>(RT) * KD * 64);
+    frag(transpose(re.Pq, Np, Nq), Nq, Np, QT, KD, PTp, 0);
+    frag(transpose(re.Vq, Nq, Np), Np, Nq, RT, KQ, VTp, 0);
+    if ((rc = upload_run(c, c->d.DTpad, DTp))) return rc;
+    if ((rc = upload_run(c, c->d.PqTpad, PTp))) return rc;
+    if ((rc = upload_run(c, c->d.VqTpad, VTp))) return rc;
   }
   if ((rc = upload_run(c, c->d.VqT, transpose(re.Vq, Nq, Np)))) return rc;
   if ((rc = upload_run(c, c->d.PqT, transpose(re.Pq, Np, Nq)))) return rc;

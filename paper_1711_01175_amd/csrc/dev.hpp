@@ -28,6 +28,10 @@ struct Dev {
   void* Lpad = nullptr;              // LIFT, one block per face
   void* Vqpad = nullptr;             // nodes -> quadrature points
   void* Pqpad = nullptr;             // quadrature points -> nodes (L2_Q projection)
+  // transposed operators in fragment order for the adjoint
+  void* DTpad = nullptr;             // Dr^T, Ds^T, Dt^T        [3][RT][NpK/4][64]
+  void* PqTpad = nullptr;            // Pq^T (quadrature rows)  [QT][NpK/4][64]
+  void* VqTpad = nullptr;            // Vq^T (node rows)        [RT][NqK/4][64]
   void* VqT = nullptr;               // [Np][Nq]
   void* PqT = nullptr;               // [Nq][Np]
   // row-major operators for the adjoint kernels
