@@ -102,6 +102,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   const int e0 = tile * E;
   const bool own = w < RT;             // this wave owns node row tile R = w
   const int R = w;
+  // own stresses [Np][SE] beside the face buffer, from the first volume
+  // direction until the last flux, when they fit in the Y region
+  constexpr bool SIGL = NfpK * SF + Np * SE <= TL::Y;
+  T* Ssig = sY + NfpK * SF;
 
   // ---- face-point gathers, one face ahead of use: own stresses and the
   // neighbour's velocity and stresses at the matching node.
@@ -119,8 +123,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         const T* so = a.sin + (e0 + e) * 6 * Np + il;
         const T* qn = a.qin + nb * 9 * Np + nn;
         const T* sn = a.sin + nb * 6 * Np + nn;
+        if constexpr (!SIGL) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) pf[p].sm[m] = so[m * Np];
+          for (int m = 0; m < 6; ++m) pf[p].sm[m] = so[m * Np];
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) pf[p].vp[c] = qn[c * Np];
 #pragma unroll
@@ -181,8 +187,17 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         const int e = x / Np, j = x % Np;
         T sg[6];
         const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+        if (!SIGL || k == 0) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) sg[m] = a.sin[ge * 6 * Np + m * Np + j];
+          for (int m = 0; m < 6; ++m) sg[m] = a.sin[ge * 6 * Np + m * Np + j];
+          if constexpr (SIGL) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) Ssig[j * SE + m * 16 + e] = sg[m];
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < 6; ++m) sg[m] = Ssig[j * SE + m * 16 + e];
+        }
         const T* g = &sgeo[e * 32 + k * 3];
         // rows of sigma in Voigt order xx,yy,zz,yz,xz,xy
         SG[j * SV + 0 * 16 + e] = g[0] * sg[0] + g[1] * sg[5] + g[2] * sg[4];
@@ -248,7 +263,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       T vm[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) vm[c] = Sv[il * SV + c * 16 + e];
-      const T* sm = pf[p].sm;
+      T smv[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) smv[m] = SIGL ? Ssig[il * SE + m * 16 + e] : pf[p].sm[m];
+      const T* sm = smv;
       const T* sp = pf[p].sp;
       const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2], sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
                        sm[4] * n[0] + sm[3] * n[1] + sm[2] * n[2]};
@@ -280,9 +298,25 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   }
 
   // ---- right-hand side to LDS: velocity rows [NpK][SV] for the mass
-  // inverse, strain rows [NpK][SE] (overwritten in place by the new strains)
+  // inverse and strain rows [NpK][SE].  When both fit in the Y region the
+  // staged old velocities stay in place for the update (no second global
+  // read of them) and the new strains go to the X region; otherwise the new
+  // strains overwrite their right-hand side in place.
+  constexpr bool VL = NpK * SV + NpK * SE <= TL::Y;
   T* Srv = sY;  // (the face buffer is free after the lift)
+  T* Ser = VL ? sY + NpK * SV : sX;
   T* Se = sX;
+  constexpr int NPU = (E * Np + NT - 1) / NT;
+  T vold[NPU][3];
+  if constexpr (VL) {
+#pragma unroll
+    for (int p = 0; p < NPU; ++p) {
+      const int x = tid + p * NT;
+      const int e = x / Np, i = x % Np;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vold[p][c] = x < E * Np ? Sv[i * SV + c * 16 + e] : T(0);
+    }
+  }
   if (own) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -291,16 +325,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) Srv[i * SV + c * 16 + lr] = rhs[c][r];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) Se[i * SE + m * 16 + lr] = rhs[3 + m][r];
+        for (int m = 0; m < 6; ++m) Ser[i * SE + m * 16 + lr] = rhs[3 + m][r];
       }
     }
   }
   __syncthreads();
+  if constexpr (VL) {
+    // K-padding rows of the new strains (read by the V_Q products)
+    for (int x = tid; x < (NpK - Np) * SE; x += NT) Se[Np * SE + x] = T(0);
+  }
 
   // ---- per (element, node): density-weighted mass inverse on the velocity
   // rows, point source, LSRK update of all nine fields with coalesced
-  // accesses; the new strains replace their right-hand side in LDS.
-  constexpr int NPU = (E * Np + NT - 1) / NT;
+  // accesses; the new strains go to LDS for the projection.
 #pragma unroll
   for (int p = 0; p < NPU; ++p) {
     const int x = tid + p * NT;
@@ -314,7 +351,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       rv[c] = (MODE != 0) ? a.out[base + c * Np] : T(0);
-      qv[c] = (MODE != 0) ? a.qin[base + c * Np] : T(0);
+      qv[c] = (MODE != 0) ? ((VL && c < 3) ? vold[p][c < 3 ? c : 0] : a.qin[base + c * Np]) : T(0);
     }
     T o[9];
     o[0] = 0;
@@ -348,7 +385,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       for (int c = 0; c < 3; ++c) a.rhsv[static_cast<int64_t>(ge) * 3 * Np + c * Np + i] = o[c];
     }
 #pragma unroll
-    for (int m = 0; m < 6; ++m) o[3 + m] = Se[i * SE + m * 16 + e];
+    for (int m = 0; m < 6; ++m) o[3 + m] = Ser[i * SE + m * 16 + e];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       if (MODE == 0) {
