@@ -31,13 +31,14 @@ struct AdjDev {
 
 // qbar += scale * L^T y; if q is given also g += scale * y . d(L q + f)/d theta
 // (s = sigma_h(q); rhs holds the velocity rows of L q + f at element stride
-// rhs_stride values, component c at offset c Np).
+// rhs_stride values, component c at offset c Np).  If rupd is given it must
+// be y, and afterwards y = ra y + rb qbar (with the updated qbar).
 hipError_t launch_adjoint(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
-                          const void* rhs, int rhs_stride, void* qbar, double* g, double scale, hipStream_t st);
+                          const void* rhs, int rhs_stride, void* qbar, double* g, double scale, void* rupd,
+                          double ra, double rb, hipStream_t st);
 // qbar_v += scale * (receiver basis row)^T resid for every receiver
 hipError_t launch_adj_receivers(const Dev& d, void* qbar, const double* resid, int nr, double scale,
                                 hipStream_t st);
 hipError_t launch_axpy(int prec, void* y, const void* x, double a, int64_t n, hipStream_t st);
-hipError_t launch_scal(int prec, void* y, double a, int64_t n, hipStream_t st);
 
 }  // namespace ewdg

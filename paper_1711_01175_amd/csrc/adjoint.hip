@@ -74,7 +74,22 @@ struct AdjArgs {
   const T* Vqpad;      // Vq     [QT][NpK/4][64]
   int64_t K;
   T scale;
+  // if set (it is y itself): after qbar is updated, rupd = ra rupd + rb qbar
+  // for the kernel's own elements (the scaling and the next axpy of the
+  // reverse Runge-Kutta recurrence, fused)
+  T* rupd;
+  T ra, rb;
 };
+
+// rupd = ra rupd + rb qbar over the elements [e0, e0 + ne) of one workgroup;
+// call after a barrier that follows every read of y and write of qbar.
+template <typename T, int Np>
+__device__ __forceinline__ void fused_recurrence(const AdjArgs<T>& a, int64_t e0, int ne, int tid, int nt) {
+  for (int x = tid; x < ne * 9 * Np; x += nt) {
+    const int64_t i = e0 * 9 * Np + x;
+    a.rupd[i] = a.ra * a.rupd[i] + a.rb * a.qbar[i];
+  }
+}
 
 template <typename T, int N>
 struct AdjCfg {
@@ -397,7 +412,13 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
       pr[e * Np + j] = -p;
     }
   }
-  if (!a.q || !a.g) return;
+  if (!a.q || !a.g) {
+    if (a.rupd) {
+      __syncthreads();
+      fused_recurrence<T, Np>(a, e0, ne, tid, NT);
+    }
+    return;
+  }
   __syncthreads();
   // per-element gradient in FP64, summed in a fixed order
   for (int e = tid; e < ne; e += NT) {
@@ -423,6 +444,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjB(AdjArgs<T> a) {
     a.g[(e0 + e) * 3 + 1] += sc * gl;
     a.g[(e0 + e) * 3 + 2] += sc * gm;
   }
+  if (a.rupd) fused_recurrence<T, Np>(a, e0, ne, tid, NT);   // y was last read before the barrier above
 }
 
 // Pass B on the matrix cores, for a tile of 16 elements (matrix columns are
@@ -747,7 +769,13 @@ __global__ __launch_bounds__((Tile<N>::NT), EWDG_ADJ_OCC) void k_adjB_mma(AdjArg
     const T v = (c < 3) ? SBV[j * SB + (6 + c) * 16 + e] : Seb[j * SE + (c - 3) * 16 + e];
     a.qbar[e0 * 9 * Np + x] += a.scale * v;
   }
-  if (!grad) return;
+  if (!grad) {
+    if (a.rupd) {
+      __syncthreads();
+      fused_recurrence<T, Np>(a, e0, ne, tid, NT);
+    }
+    return;
+  }
   T* pr = r3;    // [E][Np] density partials (the chunk buffer is free)
   for (int x = tid; x < ne * Np; x += NT) {
     const int e = x / Np, j = x % Np;
@@ -778,6 +806,7 @@ __global__ __launch_bounds__((Tile<N>::NT), EWDG_ADJ_OCC) void k_adjB_mma(AdjArg
     a.g[(e0 + e) * 3 + 1] += sc * gl;
     a.g[(e0 + e) * 3 + 2] += sc * gm;
   }
+  if (a.rupd) fused_recurrence<T, Np>(a, e0, ne, tid, NT);   // y was last read before the barrier above
 }
 
 // qbar_v(receiver element) += scale * l(x_r) resid_r, receivers in order.
@@ -802,14 +831,9 @@ __global__ __launch_bounds__(256) void k_axpy(T* y, const T* x, T a, int64_t n) 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_scal(T* y, T a, int64_t n) {
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * 256)
-    y[i] *= a;
-}
-
-template <typename T>
 static AdjArgs<T> adj_args(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
-                           const void* rhs, int rhs_es, void* qbar, double* g, double scale) {
+                           const void* rhs, int rhs_es, void* qbar, double* g, double scale, void* rupd,
+                           double ra, double rb) {
   AdjArgs<T> a;
   a.y = static_cast<const T*>(y);
   a.q = static_cast<const T*>(q);
@@ -842,15 +866,18 @@ static AdjArgs<T> adj_args(const Dev& d, const AdjDev& ad, const void* y, const 
   a.Vqpad = static_cast<const T*>(d.Vqpad);
   a.K = d.K;
   a.scale = static_cast<T>(scale);
+  a.rupd = static_cast<T*>(rupd);
+  a.ra = static_cast<T>(ra);
+  a.rb = static_cast<T>(rb);
   return a;
 }
 
 template <typename T, int N>
 static hipError_t adjoint_impl(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
                                const void* rhs, int rhs_es, void* qbar, double* g, double scale,
-                               hipStream_t st) {
+                               void* rupd, double ra, double rb, hipStream_t st) {
   using C = AdjCfg<T, N>;
-  const AdjArgs<T> a = adj_args<T>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale);
+  const AdjArgs<T> a = adj_args<T>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale, rupd, ra, rb);
   const unsigned grid = static_cast<unsigned>((d.K + C::E - 1) / C::E);
   hipLaunchKernelGGL((k_adjA<T, N>), dim3(grid), dim3(C::NT), 0, st, a);
   hipError_t e = hipGetLastError();
@@ -865,11 +892,15 @@ static hipError_t adjoint_impl(const Dev& d, const AdjDev& ad, const void* y, co
 }
 
 hipError_t launch_adjoint(const Dev& d, const AdjDev& ad, const void* y, const void* q, const void* s,
-                          const void* rhs, int rhs_es, void* qbar, double* g, double scale, hipStream_t st) {
+                          const void* rhs, int rhs_es, void* qbar, double* g, double scale, void* rupd, double ra,
+                          double rb, hipStream_t st) {
+  if (rupd && rupd != y) return hipErrorInvalidValue;   // the fused recurrence updates y itself
   if (d.prec == 32) {
-    EWDG_DISPATCH(d.N, return (adjoint_impl<float, NN>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale, st)));
+    EWDG_DISPATCH(d.N,
+                  return (adjoint_impl<float, NN>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale, rupd, ra, rb, st)));
   }
-  EWDG_DISPATCH(d.N, return (adjoint_impl<double, NN>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale, st)));
+  EWDG_DISPATCH(d.N,
+                return (adjoint_impl<double, NN>(d, ad, y, q, s, rhs, rhs_es, qbar, g, scale, rupd, ra, rb, st)));
 }
 
 hipError_t launch_adj_receivers(const Dev& d, void* qbar, const double* resid, int nr, double scale,
@@ -893,16 +924,6 @@ hipError_t launch_axpy(int prec, void* y, const void* x, double a, int64_t n, hi
   else
     hipLaunchKernelGGL((k_axpy<double>), dim3(grid), dim3(256), 0, st, static_cast<double*>(y),
                        static_cast<const double*>(x), a, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_scal(int prec, void* y, double a, int64_t n, hipStream_t st) {
-  const unsigned grid = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 65536));
-  if (prec == 32)
-    hipLaunchKernelGGL((k_scal<float>), dim3(grid), dim3(256), 0, st, static_cast<float*>(y),
-                       static_cast<float>(a), n);
-  else
-    hipLaunchKernelGGL((k_scal<double>), dim3(grid), dim3(256), 0, st, static_cast<double*>(y), a, n);
   return hipGetLastError();
 }
 

@@ -880,7 +880,9 @@ int ewdg_rhs_adjoint(ewdg_ctx* c, double t, const void* q, const void* y, void* 
   if (g) {
     if ((rc = c->hip(hipMemsetAsync(g, 0, 3 * static_cast<size_t>(c->mesh.K) * 8, c->stream), "memset"))) return rc;
   }
-  return c->hip(launch_adjoint(c->d, c->ad, y, q, s, c->ad.rhs, 9 * c->re.Np, LTy, g, 1.0, c->stream), "adjoint");
+  return c->hip(launch_adjoint(c->d, c->ad, y, q, s, c->ad.rhs, 9 * c->re.Np, LTy, g, 1.0, nullptr, 0.0, 0.0,
+                               c->stream),
+                "adjoint");
 }
 
 int ewdg_forward_misfit(ewdg_ctx* c, double dt, int nsteps, const double* data, double* J) {
@@ -961,15 +963,19 @@ int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
                                               c->stream), "adjoint receivers")))
           return rc;
       }
+      // reverse stage i: rbar += b_i qbar; qbar += dt L^T rbar (and the
+      // gradient); rbar *= a_i.  The scaling and the next stage's axpy
+      // (b_{i-1}; none after stage 1, whose a_1 = 0 clears rbar) run inside
+      // the adjoint kernel; only the first axpy of a step, after the
+      // misfit term, is a launch of its own.
+      if ((rc = c->hip(launch_axpy(c->prec, a.rbar, a.qbar, kRkB[4], static_cast<int64_t>(n9), c->stream), "axpy")))
+        return rc;
       for (int i = 4; i >= 0; --i) {
         const size_t k = 5 * static_cast<size_t>(m) + i;
-        if ((rc = c->hip(launch_axpy(c->prec, a.rbar, a.qbar, kRkB[i], static_cast<int64_t>(n9), c->stream), "axpy")))
-          return rc;
         if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, slot(a.st_q, c, 9, k), slot(a.st_s, c, 6, k),
-                                        slot(a.rhsv, c, 3, k), 3 * c->re.Np, a.qbar, a.g, dt, c->stream),
+                                        slot(a.rhsv, c, 3, k), 3 * c->re.Np, a.qbar, a.g, dt, a.rbar, kRkA[i],
+                                        i > 0 ? kRkB[i - 1] : 0.0, c->stream),
                          "adjoint")))
-          return rc;
-        if ((rc = c->hip(launch_scal(c->prec, a.rbar, kRkA[i], static_cast<int64_t>(n9), c->stream), "scal")))
           return rc;
       }
     }

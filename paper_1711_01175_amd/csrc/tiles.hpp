@@ -81,8 +81,12 @@ struct Tile {
   static constexpr int NW = RT > 4 ? 8 : 4;     // waves: at most one node row tile each
   static constexpr int NT = 64 * NW;
   // LDS regions (in values): X holds v and the contravariant stresses, later
-  // the velocity right-hand side and then the new strains; Y holds one face's
-  // interface corrections, later the stresses at the quadrature points.
+  // the strains (right-hand side, then new values) and the new sigma_h; Y
+  // holds one face's interface corrections, then the velocity right-hand
+  // side, later the stresses at the quadrature points.  Where they fit, Y
+  // also keeps the element's own stresses beside the face buffer and the
+  // strain right-hand side beside the velocity one (v then stays in X until
+  // the update).
   // LDS row strides (values) of the B-operand buffers: 3, 6, 9 and 6 fields
   // of 16 element columns, padded against bank conflicts
   static constexpr int SV = EWDG_SV, SE = EWDG_SE, SF = EWDG_SF, SQ = EWDG_SQ;

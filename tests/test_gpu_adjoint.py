@@ -138,9 +138,8 @@ def test_parameter_gradient_vs_central_differences(N):
     assert worst <= 1e-6 * scale
 
 
-def _misfit_case():
+def _misfit_case(N=2, n=3, nsteps=15):
     from oracle import adjoint, timestep
-    N, n, nsteps = 2, 3, 15
     op, EToV, VXYZ, xyz, mat = oracle_case(N, n, shuffle_seed=1, jump_seed=3)
     src = timestep.Source(np.array(SRC["xs"]), np.array(SRC["direction"]), SRC["amp"], SRC["f0"], SRC["t0"])
     rec = np.array([[0.3, -0.2, 0.1], [-0.4, 0.5, -0.6]])
@@ -176,9 +175,13 @@ def test_misfit_gradient_vs_oracle_complex_step():
     assert gerr <= 1e-9
 
 
-def test_initial_state_gradient_vs_central_differences():
+@pytest.mark.parametrize("N,n,nsteps", [(2, 3, 15), (5, 3, 10)])
+def test_initial_state_gradient_vs_central_differences(N, n, nsteps):
+    """dJ/dq0 from the reverse sweep against central differences (J is
+    quadratic in q0).  N=5 in FP64 runs the LDS-staged pass B (its
+    matrix-core tile does not fit in LDS), N=2 the matrix-core one."""
     torch = _torch()
-    N, op, EToV, VXYZ, mat, src, rec, dt, nsteps, data = _misfit_case()
+    N, op, EToV, VXYZ, mat, src, rec, dt, nsteps, data = _misfit_case(N, n, nsteps)
     c = _ctx(N, 64, EToV, VXYZ, mat, max_rec=2, max_steps=nsteps, every=6)
     c.set_source(src.xs, src.direction, src.amp, src.f0, src.t0)
     c.set_receivers(rec)
@@ -195,7 +198,7 @@ def test_initial_state_gradient_vs_central_differences():
         Js.append(c.forward_misfit(dt, nsteps, data))
     fd = (Js[0] - Js[1]) / (2 * h)
     ad = _dot(qbar, d)
-    _report("dJ/dq0", adjoint=ad, fd=fd, rel=abs(ad - fd) / abs(fd))
+    _report("dJ/dq0", N=N, adjoint=ad, fd=fd, rel=abs(ad - fd) / abs(fd))
     assert abs(ad - fd) <= 1e-10 * abs(fd)
 
 
