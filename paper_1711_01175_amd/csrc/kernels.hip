@@ -74,8 +74,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
   return (bid % 8) * (nblk / 8) + bid / 8;
 }
 
-// Face-point data gathered for one face ahead of its use: own stresses and
-// the neighbour's velocity and stresses at the matching node.
+// Face-point data gathered for one face ahead of its use: the neighbour's
+// velocity and stresses at the matching node, and the own stresses where the
+// tile does not keep them in LDS.
 template <typename T>
 struct FacePt {
   T sm[6], vp[3], sp[6], zp, zs;
@@ -107,8 +108,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   constexpr bool SIGL = NfpK * SF + Np * SE <= TL::Y;
   T* Ssig = sY + NfpK * SF;
 
-  // ---- face-point gathers, one face ahead of use: own stresses and the
-  // neighbour's velocity and stresses at the matching node.
+  // ---- face-point gathers, one face ahead of use: the neighbour's velocity
+  // and stresses at the matching node (and the own stresses when they are
+  // not kept in LDS).
   auto gather = [&](int f, FacePt<T>* pf) {
 #pragma unroll
     for (int p = 0; p < FPT; ++p) {
