@@ -19,9 +19,11 @@
 // Tuning constants (measured on MI355X at N=4): EWDG_ADJ_LDS caps the LDS of
 // one workgroup in KiB (fewer elements per workgroup, more workgroups per
 // CU); EWDG_ADJ_UNROLL > 0 forces that unroll factor on the inner loops;
-// EWDG_ADJ_QC is the number of quadrature rows per projection chunk of the
-// matrix-core pass B (32 rather than 64 halves its chunk registers and LDS:
-// at N=4 FP32 3 waves per SIMD instead of 2, 7 % less gradient time);
+// EWDG_ADJ_QC32 / EWDG_ADJ_QC64 are the quadrature rows per projection chunk
+// of the matrix-core pass B in FP32 / FP64 (in FP32, 32 rather than 64 halves
+// the chunk registers and LDS: at N=4 3 waves per SIMD instead of 2, 7 % less
+// gradient time; FP64 stays at one wave per SIMD either way and is 8 % faster
+// with 64);
 // EWDG_ADJ_OCC is its waves-per-SIMD target; EWDG_ADJ_MMA = 0 selects the
 // LDS-staged pass B everywhere.
 #ifndef EWDG_ADJ_LDS
@@ -33,8 +35,11 @@
 #ifndef EWDG_ADJ_MMA
 #define EWDG_ADJ_MMA 1
 #endif
-#ifndef EWDG_ADJ_QC
-#define EWDG_ADJ_QC 32
+#ifndef EWDG_ADJ_QC32
+#define EWDG_ADJ_QC32 32
+#endif
+#ifndef EWDG_ADJ_QC64
+#define EWDG_ADJ_QC64 64
 #endif
 #ifndef EWDG_ADJ_OCC
 #define EWDG_ADJ_OCC 2
@@ -470,7 +475,8 @@ struct AdjTile {
   using TL = Tile<N>;
   static constexpr int Np = TL::Np, Nfp = TL::Nfp, NpK = TL::NpK, E = TL::E, NW = TL::NW;
   static constexpr int SV = TL::SV, SE = TL::SE, SQ = TL::SQ;
-  static constexpr int QC = TL::NqR < EWDG_ADJ_QC ? TL::NqR : EWDG_ADJ_QC;   // quadrature rows per chunk
+  static constexpr int QCT = sizeof(T) == 4 ? EWDG_ADJ_QC32 : EWDG_ADJ_QC64;
+  static constexpr int QC = TL::NqR < QCT ? TL::NqR : QCT;   // quadrature rows per chunk
   static constexpr int SB = 9 * 16 + 1;                       // sigma-bar (0..5) | v-bar (6..8)
   static constexpr int R1 = cmax2(2 * NpK * SV, NpK * SE);    // volume operands, own strains, epsbar
   static constexpr int R2 = NpK * SB;
