@@ -192,8 +192,20 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
  * values in the run precision (memory is traded for recomputation: a
  * smaller C needs less).  Call
  * after ewdg_bind_workspace (the receiver capacity is taken from it);
- * binding the forward workspace again or a new mesh drops the binding. */
+ * binding the forward workspace again or a new mesh drops the binding.
+ *
+ * ewdg_adjoint_workspace_bytes_overlapped: the size of the same workspace
+ * with a second segment buffer, about (ceil(max_steps/C) + 12 C + 7) * 15 K
+ * Np values.  A workspace of at least this size, given to
+ * ewdg_bind_adjoint_workspace, makes ewdg_adjoint_gradient recompute the next
+ * segment on a second HIP stream (created by the library, default priority,
+ * destroyed with the context) while the current one is reversed on the
+ * context's stream; events order the two, and the result is bit-identical
+ * to the single-buffer sweep.  Smaller workspaces run everything on the
+ * context's stream. */
 int ewdg_adjoint_workspace_bytes(const ewdg_ctx* ctx, int max_steps, int checkpoint_every, size_t* bytes);
+int ewdg_adjoint_workspace_bytes_overlapped(const ewdg_ctx* ctx, int max_steps, int checkpoint_every,
+                                            size_t* bytes);
 int ewdg_bind_adjoint_workspace(ewdg_ctx* ctx, void* device_ptr, size_t bytes, int max_steps,
                                 int checkpoint_every);
 /* LTy_dev = L^T y (the transpose of ewdg_rhs's linear part in the plain

@@ -27,6 +27,10 @@ struct AdjDev {
   void* ck_s = nullptr;      // [nck][K][6][Np]
   void* st_q = nullptr;      // [5 C + 1][K][9][Np]
   void* st_s = nullptr;      // [5 C + 1][K][6][Np]
+  // second segment buffer of the overlapped layout (null otherwise)
+  void* rhsv2 = nullptr;
+  void* st_q2 = nullptr;
+  void* st_s2 = nullptr;
 };
 
 // qbar += scale * L^T y; if q is given also g += scale * y . d(L q + f)/d theta

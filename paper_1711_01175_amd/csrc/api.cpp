@@ -56,12 +56,25 @@ struct ewdg_ctx {
   AdjDev ad;
   bool adj_bound = false;
   int adj_max_steps = 0, adj_every = 0, adj_rec = 0;
+  // overlapped reverse sweep: a second segment buffer, refilled on a second
+  // stream while the current segment is reversed on the context's stream
+  bool adj_overlap = false;
+  hipStream_t adj_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   bool fwd_done = false;
   int fwd_steps = 0;
   double fwd_dt = 0.0;
   std::vector<double> step_t;  // time at the start of every recorded step
   std::string err;
 
+  ~ewdg_ctx() {
+    if (adj_stream) {
+      (void)hipStreamSynchronize(adj_stream);
+      (void)hipStreamDestroy(adj_stream);
+    }
+    for (hipEvent_t e : {ev_start, ev_rec[0], ev_rec[1], ev_rev[0], ev_rev[1]})
+      if (e) (void)hipEventDestroy(e);
+  }
   size_t tsz() const { return prec == 32 ? 4 : 8; }
   int fail(int code, const std::string& m) {
     err = m;
@@ -776,7 +789,8 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
 namespace {
 
 // Layout of the adjoint workspace; with base == nullptr only the size.
-size_t adj_layout(const ewdg_ctx* c, int max_steps, int every, int max_rec, char* base, AdjDev* ad) {
+size_t adj_layout(const ewdg_ctx* c, int max_steps, int every, int max_rec, char* base, AdjDev* ad,
+                  bool overlap) {
   const size_t K = static_cast<size_t>(c->mesh.K), Np = c->re.Np, Nfp = c->re.Nfp, ts = c->tsz();
   const size_t nck = (static_cast<size_t>(max_steps) + every - 1) / every;
   size_t off = 0;
@@ -803,6 +817,11 @@ size_t adj_layout(const ewdg_ctx* c, int max_steps, int every, int max_rec, char
   const size_t nst = static_cast<size_t>(every) * 5 + 1;
   a.st_q = take(nst * 9 * Np * K * ts);
   a.st_s = take(nst * 6 * Np * K * ts);
+  if (overlap) {   // the second segment buffer
+    a.rhsv2 = take(static_cast<size_t>(every) * 5 * 3 * Np * K * ts);
+    a.st_q2 = take(nst * 9 * Np * K * ts);
+    a.st_s2 = take(nst * 6 * Np * K * ts);
+  }
   if (ad) *ad = a;
   return off;
 }
@@ -812,17 +831,17 @@ void* slot(void* base, const ewdg_ctx* c, int m, size_t i) {
   return static_cast<char*>(base) + i * m * c->re.Np * static_cast<size_t>(c->mesh.K) * c->tsz();
 }
 
-int copy_dev(ewdg_ctx* c, void* dst, const void* src, int m) {
+int copy_dev(ewdg_ctx* c, void* dst, const void* src, int m, hipStream_t st = nullptr) {
   const size_t bytes = static_cast<size_t>(m) * c->re.Np * c->mesh.K * c->tsz();
-  return c->hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "snapshot copy");
+  return c->hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st ? st : c->stream), "snapshot copy");
 }
 
 // One LSRK stage on caller buffers (the context state is untouched); with
 // rhsv the velocity rows of the stage's right-hand side are kept as well.
 int stage_on(ewdg_ctx* c, int i, double dt, double tn, const void* qin, const void* sin, void* qout, void* sout,
-             void* rhsv = nullptr) {
+             void* rhsv = nullptr, hipStream_t st = nullptr) {
   const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, tn + kRkC[i] * dt);
-  return c->hip(launch_stage(c->d, rhsv ? 2 : 1, qin, sin, qout, sout, c->ad.res, sc, c->stream, rhsv),
+  return c->hip(launch_stage(c->d, rhsv ? 2 : 1, qin, sin, qout, sout, c->ad.res, sc, st ? st : c->stream, rhsv),
                 "recompute stage");
 }
 
@@ -839,7 +858,14 @@ extern "C" {
 int ewdg_adjoint_workspace_bytes(const ewdg_ctx* c, int max_steps, int checkpoint_every, size_t* bytes) {
   if (int rc = need(c, true, true, false)) return rc;
   if (!bytes || max_steps < 1 || checkpoint_every < 1) return EWDG_EINVAL;
-  *bytes = adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr);
+  *bytes = adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr, false);
+  return EWDG_OK;
+}
+
+int ewdg_adjoint_workspace_bytes_overlapped(const ewdg_ctx* c, int max_steps, int checkpoint_every, size_t* bytes) {
+  if (int rc = need(c, true, true, false)) return rc;
+  if (!bytes || max_steps < 1 || checkpoint_every < 1) return EWDG_EINVAL;
+  *bytes = adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr, true);
   return EWDG_OK;
 }
 
@@ -848,9 +874,16 @@ int ewdg_bind_adjoint_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_st
   if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
     return c->fail(EWDG_EINVAL, "adjoint workspace must be a non-null 256-byte aligned device pointer");
   if (max_steps < 1 || checkpoint_every < 1) return c->fail(EWDG_EINVAL, "max_steps and checkpoint_every must be >= 1");
-  if (bytes < adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr))
+  if (bytes < adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr, false))
     return c->fail(EWDG_ENOMEM, "adjoint workspace smaller than ewdg_adjoint_workspace_bytes");
-  adj_layout(c, max_steps, checkpoint_every, c->max_rec, static_cast<char*>(ptr), &c->ad);
+  const bool overlap = bytes >= adj_layout(c, max_steps, checkpoint_every, c->max_rec, nullptr, nullptr, true);
+  if (overlap && !c->adj_stream) {
+    if (int rc = c->hip(hipStreamCreateWithFlags(&c->adj_stream, hipStreamNonBlocking), "adjoint stream")) return rc;
+    for (hipEvent_t* e : {&c->ev_start, &c->ev_rec[0], &c->ev_rec[1], &c->ev_rev[0], &c->ev_rev[1]})
+      if (int rc = c->hip(hipEventCreateWithFlags(e, hipEventDisableTiming), "adjoint event")) return rc;
+  }
+  c->adj_overlap = overlap;
+  adj_layout(c, max_steps, checkpoint_every, c->max_rec, static_cast<char*>(ptr), &c->ad, overlap);
   // the recomputation register is scaled by a_1 = 0 at every step start, so
   // it only has to hold finite values
   if (int rc = c->hip(hipMemsetAsync(c->ad.res, 0, 9 * static_cast<size_t>(c->re.Np) * c->mesh.K * c->tsz(),
@@ -939,22 +972,56 @@ int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
   if ((rc = c->hip(hipMemsetAsync(a.rbar, 0, n9 * c->tsz(), c->stream), "memset"))) return rc;
   if ((rc = c->hip(hipMemsetAsync(a.g, 0, 3 * static_cast<size_t>(K) * 8, c->stream), "memset"))) return rc;
   const int nseg = (NS + C - 1) / C;
-  for (int seg = nseg - 1; seg >= 0; --seg) {
+  // Segment buffers: with the overlapped layout segment seg uses buffer
+  // seg & 1, and segment seg - 1 is recomputed on the second stream while
+  // segment seg is reversed on the context's stream (events order the
+  // hand-over of each buffer); otherwise one buffer, all on one stream.
+  const bool ov = c->adj_overlap;
+  hipStream_t rs = ov ? c->adj_stream : c->stream;
+  auto buf_q = [&](int seg) { return (ov && (seg & 1)) ? a.st_q2 : a.st_q; };
+  auto buf_s = [&](int seg) { return (ov && (seg & 1)) ? a.st_s2 : a.st_s; };
+  auto buf_v = [&](int seg) { return (ov && (seg & 1)) ? a.rhsv2 : a.rhsv; };
+  // every stage input of a segment and the velocity rows of every stage
+  // right-hand side, recomputed from the segment's checkpoint; slot 5 m + i
+  // holds the input of stage i of step m
+  auto recompute = [&](int seg) -> int {
     const int s0 = seg * C, len = std::min(C, NS - s0);
-    // every stage input of the segment and the velocity rows of every stage
-    // right-hand side, recomputed from the segment's checkpoint; slot 5 m + i
-    // holds the input of stage i of step m
-    if ((rc = copy_dev(c, slot(a.st_q, c, 9, 0), slot(a.ck_q, c, 9, seg), 9))) return rc;
-    if ((rc = copy_dev(c, slot(a.st_s, c, 6, 0), slot(a.ck_s, c, 6, seg), 6))) return rc;
+    void *sq = buf_q(seg), *ss = buf_s(seg), *sv = buf_v(seg);
+    if (int r = copy_dev(c, slot(sq, c, 9, 0), slot(a.ck_q, c, 9, seg), 9, rs)) return r;
+    if (int r = copy_dev(c, slot(ss, c, 6, 0), slot(a.ck_s, c, 6, seg), 6, rs)) return r;
     for (int m = 0; m < len; ++m) {
       const double tn = c->step_t[s0 + m];
       for (int i = 0; i < 5; ++i) {
         const size_t k = 5 * static_cast<size_t>(m) + i;
-        if ((rc = stage_on(c, i, dt, tn, slot(a.st_q, c, 9, k), slot(a.st_s, c, 6, k), slot(a.st_q, c, 9, k + 1),
-                           slot(a.st_s, c, 6, k + 1), slot(a.rhsv, c, 3, k))))
-          return rc;
+        if (int r = stage_on(c, i, dt, tn, slot(sq, c, 9, k), slot(ss, c, 6, k), slot(sq, c, 9, k + 1),
+                             slot(ss, c, 6, k + 1), slot(sv, c, 3, k), rs))
+          return r;
       }
     }
+    return EWDG_OK;
+  };
+  if (ov) {
+    // the checkpoints and the cleared adjoint registers come from this stream
+    if ((rc = c->hip(hipEventRecord(c->ev_start, c->stream), "event"))) return rc;
+    if ((rc = c->hip(hipStreamWaitEvent(rs, c->ev_start, 0), "event wait"))) return rc;
+    if ((rc = recompute(nseg - 1))) return rc;
+    if ((rc = c->hip(hipEventRecord(c->ev_rec[(nseg - 1) & 1], rs), "event"))) return rc;
+  }
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * C, len = std::min(C, NS - s0);
+    if (ov) {
+      if (seg >= 1) {
+        const int b = (seg - 1) & 1;
+        // buffer b was last read by the reverse sweep of segment seg + 1
+        if (seg + 1 <= nseg - 1 && (rc = c->hip(hipStreamWaitEvent(rs, c->ev_rev[b], 0), "event wait"))) return rc;
+        if ((rc = recompute(seg - 1))) return rc;
+        if ((rc = c->hip(hipEventRecord(c->ev_rec[b], rs), "event"))) return rc;
+      }
+      if ((rc = c->hip(hipStreamWaitEvent(c->stream, c->ev_rec[seg & 1], 0), "event wait"))) return rc;
+    } else if ((rc = recompute(seg))) {
+      return rc;
+    }
+    void *sq = buf_q(seg), *ss = buf_s(seg), *sv = buf_v(seg);
     for (int m = len - 1; m >= 0; --m) {
       const int n = s0 + m;
       // misfit term of the state after step n
@@ -972,13 +1039,15 @@ int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
         return rc;
       for (int i = 4; i >= 0; --i) {
         const size_t k = 5 * static_cast<size_t>(m) + i;
-        if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, slot(a.st_q, c, 9, k), slot(a.st_s, c, 6, k),
-                                        slot(a.rhsv, c, 3, k), 3 * c->re.Np, a.qbar, a.g, dt, a.rbar, kRkA[i],
+        if ((rc = c->hip(launch_adjoint(c->d, a, a.rbar, slot(sq, c, 9, k), slot(ss, c, 6, k),
+                                        slot(sv, c, 3, k), 3 * c->re.Np, a.qbar, a.g, dt, a.rbar, kRkA[i],
                                         i > 0 ? kRkB[i - 1] : 0.0, c->stream),
                          "adjoint")))
           return rc;
       }
     }
+    // this segment's buffer may be refilled once its reverse sweep is done
+    if (ov && (rc = c->hip(hipEventRecord(c->ev_rev[seg & 1], c->stream), "event"))) return rc;
   }
   if ((rc = c->hip(hipMemcpyAsync(g, a.g, 3 * static_cast<size_t>(K) * 8, hipMemcpyDefault, c->stream), "g copy")))
     return rc;

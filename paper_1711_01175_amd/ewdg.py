@@ -56,6 +56,7 @@ SIGNATURES = {
     "ewdg_batch_table_bytes": [_c_i, ctypes.POINTER(_c_sz)],
     "ewdg_step_batch": [ctypes.POINTER(_c_p), _c_i, ctypes.POINTER(_c_d), _c_i, _c_p, _c_sz, _c_p],
     "ewdg_adjoint_workspace_bytes": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
+    "ewdg_adjoint_workspace_bytes_overlapped": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
     "ewdg_bind_adjoint_workspace": [_c_p, _c_p, _c_sz, _c_i, _c_i],
     "ewdg_rhs_adjoint": [_c_p, _c_d, _c_p, _c_p, _c_p, _c_p],
     "ewdg_forward_misfit": [_c_p, _c_d, _c_i, _c_p, _P_d],
@@ -308,15 +309,17 @@ class Context:
         return e.value
 
     # -------------------------------------------------------------- adjoint
-    def adjoint_workspace_bytes(self, max_steps, checkpoint_every=50):
+    def adjoint_workspace_bytes(self, max_steps, checkpoint_every=50, overlapped=False):
+        """Bytes of the adjoint workspace; overlapped=True adds the second
+        segment buffer that lets the recomputation run on a second stream."""
         b = _c_sz()
-        self._check(self.lib.ewdg_adjoint_workspace_bytes(self.h, int(max_steps), int(checkpoint_every),
-                                                          ctypes.byref(b)), "adjoint_workspace_bytes")
+        fn = self.lib.ewdg_adjoint_workspace_bytes_overlapped if overlapped else self.lib.ewdg_adjoint_workspace_bytes
+        self._check(fn(self.h, int(max_steps), int(checkpoint_every), ctypes.byref(b)), "adjoint_workspace_bytes")
         return b.value
 
-    def bind_adjoint_workspace(self, max_steps, checkpoint_every=50, buffer=None):
+    def bind_adjoint_workspace(self, max_steps, checkpoint_every=50, buffer=None, overlapped=True):
         torch = _torch()
-        nbytes = self.adjoint_workspace_bytes(max_steps, checkpoint_every)
+        nbytes = self.adjoint_workspace_bytes(max_steps, checkpoint_every, overlapped)
         if buffer is None:
             buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self._check(self.lib.ewdg_bind_adjoint_workspace(self.h, _ptr(buffer), buffer.numel() * buffer.element_size(),

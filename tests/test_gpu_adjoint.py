@@ -175,6 +175,37 @@ def test_misfit_gradient_vs_oracle_complex_step():
     assert gerr <= 1e-9
 
 
+def test_overlapped_sweep_is_bitwise_single_buffer_sweep():
+    """The reverse sweep with the second segment buffer (next segment
+    recomputed on a second stream) gives the same bits as the single-buffer
+    sweep: 15 steps in segments of 4 (ragged last), FP32 and FP64."""
+    torch = _torch()
+    import paper_1711_01175_amd as P
+    N, op, EToV, VXYZ, mat, src, rec, dt, nsteps, data = _misfit_case()
+    for prec in (32, 64):
+        out = {}
+        for overlapped in (False, True):
+            c = P.Context(N, prec)
+            c.set_mesh(EToV, VXYZ)
+            c.bind_workspace(2, nsteps)
+            c.set_material(*mat)
+            ws = c.bind_adjoint_workspace(nsteps, 4, overlapped=overlapped)
+            assert ws.numel() == c.adjoint_workspace_bytes(nsteps, 4, overlapped)
+            c.set_source(src.xs, src.direction, src.amp, src.f0, src.t0)
+            c.set_receivers(rec)
+            gen = torch.Generator(device="cuda").manual_seed(5)
+            q0 = 0.1 * torch.randn((c.K, 9, c.Np), dtype=c.torch_dtype, device="cuda", generator=gen)
+            c.set_state(q0, 0.1)
+            J = c.forward_misfit(dt, nsteps, data)
+            g, qbar = c.adjoint_gradient(want_qbar0=True)
+            out[overlapped] = (J, g.cpu().numpy(), qbar.cpu().numpy())
+            c.close()
+        _report("overlap", prec=prec, J=out[True][0], g_max=float(np.abs(out[True][1]).max()))
+        assert out[True][0] == out[False][0]
+        assert np.array_equal(out[True][1], out[False][1])
+        assert np.array_equal(out[True][2], out[False][2])
+
+
 @pytest.mark.parametrize("N,n,nsteps", [(2, 3, 15), (5, 3, 10)])
 def test_initial_state_gradient_vs_central_differences(N, n, nsteps):
     """dJ/dq0 from the reverse sweep against central differences (J is
