@@ -126,6 +126,31 @@ def probe_copy(nbytes=2 << 30, reps=5):
                       "seconds": s, "GBs_read_plus_write": 2 * nbytes / s / 1e9}), flush=True)
 
 
+def probe_bandwidth(nbytes=4 << 30, reps=10):
+    """Achievable HBM rates of plain torch kernels on nbytes FP32 tensors:
+    elementwise x + 1 (read + write), fill (write), copy (read + write) and
+    sum (read)."""
+    import torch
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    out = {"probe": "bandwidth", "bytes": nbytes}
+    for name, fn, moved in (("add_read_plus_write", lambda: torch.add(x, 1.0, out=y), 2 * nbytes),
+                            ("fill_write", lambda: y.fill_(1.0), nbytes),
+                            ("copy_read_plus_write", lambda: y.copy_(x), 2 * nbytes),
+                            ("sum_read", lambda: x.sum(), nbytes)):
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        out[name + "_GBs"] = round(moved / (ev0.elapsed_time(ev1) * 1e-3 / reps) / 1e9, 1)
+    print(json.dumps(out), flush=True)
+
+
 def run_serving(full=False):
     """Continuous-batching serving of a seeded stream of independent solves.
 
@@ -280,15 +305,20 @@ def main():
                     help="run only the FP32 adjoint leg and print its JSON (for profiling)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="time a plain device copy of 2 GiB instead (HBM calibration)")
+    ap.add_argument("--probe-bandwidth", action="store_true",
+                    help="time plain torch kernels on 4 GiB tensors instead (achievable HBM rates)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(how the path would shard is described in the design notes).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(the design notes describe how the path would shard).", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.probe_copy:
         probe_copy()
+        return
+    if args.probe_bandwidth:
+        probe_bandwidth()
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": run_adjoint(check_fp64=False)}), flush=True)
