@@ -166,8 +166,15 @@ int ewdg_energy(ewdg_ctx* ctx, double* E);
  * bitwise identical alone or in any mix).  dts[i] is context i's step; all
  * advance nsteps steps, recording their receivers.  table_dev is caller-
  * owned device memory of at least ewdg_batch_table_bytes(n) bytes holding
- * the per-request launch table; all work is enqueued on hip_stream (the
- * contexts' own streams are not used).  A context may appear only once.
+ * the per-request launch table.  With at least nsteps times that size
+ * rounded up to 256 bytes, the tables of all steps are uploaded at once and
+ * each (degree, precision) group runs on a HIP stream of its own (created by
+ * the library at first use, default priority), forked from and joined back
+ * into hip_stream, so that the groups' launches overlap; otherwise all work
+ * is enqueued on hip_stream, one table upload per step.  Either way the
+ * work is ordered after earlier work on hip_stream and before later work on
+ * it (the contexts' own streams are not used).  A context may appear only
+ * once.  Calls from several host threads must not overlap.
  * Errors are reported through the return code; the message of the failing
  * context is in its ewdg_last_error. */
 int ewdg_batch_table_bytes(int n, size_t* bytes);

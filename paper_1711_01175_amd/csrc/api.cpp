@@ -692,6 +692,36 @@ int ewdg_energy(ewdg_ctx* c, double* E) {
 
 }  // extern "C"
 
+namespace {
+
+// One stream per (degree, precision) group of ewdg_step_batch, created on
+// first use (default priority) and kept for the life of the process (the
+// runtime releases them at exit), with a completion event each.
+struct GroupStream {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+};
+struct BatchStreams {
+  hipEvent_t fork = nullptr;
+  std::map<std::pair<int, int>, GroupStream> g;
+  GroupStream* get(int N, int prec) {
+    GroupStream& x = g[{N, prec}];
+    if (!x.s && hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (!x.done && hipEventCreateWithFlags(&x.done, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return &x;
+  }
+};
+BatchStreams& batch_streams() {
+  static BatchStreams* b = [] {
+    auto* p = new BatchStreams;
+    (void)hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    return p;
+  }();
+  return *b;
+}
+
+}  // namespace
+
 extern "C" {
 
 // Per step the table holds, for each of the 5 stages, n argument records
@@ -730,26 +760,39 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
   for (int i = 0; i < n; ++i) groups[{ctxs[i]->N, ctxs[i]->prec}].push_back(i);
   const size_t rec = batch_record_bytes();
   const int E = stage_tile_elems();
-  std::vector<char> host(need_b, 0);
+  // With room for every step's table (nsteps * stride bytes) all tables go
+  // up in one copy and each group runs its steps on a stream of its own
+  // (groups share no data, so their launches overlap on the device);
+  // otherwise one table per step on hip_stream.
+  const size_t stride = (need_b + 255) / 256 * 256;
+  const bool whole = table_bytes / stride >= static_cast<size_t>(nsteps);
+  struct Launch { int N, prec, nreq, ntiles, group; size_t args_off, tiles_off; };
+  std::vector<char> host((whole ? static_cast<size_t>(nsteps) : 1) * stride, 0);
   char* dev = static_cast<char*>(table_dev);
-  for (int step = 0; step < nsteps; ++step) {
-    // table for the five stages of this step
-    struct Launch { int N, prec, nreq, ntiles; size_t args_off, tiles_off; };
-    std::vector<Launch> launches;
-    size_t off = 0;
+  std::vector<int> cur(n);
+  std::vector<double> tt(n);
+  for (int i = 0; i < n; ++i) {
+    cur[i] = ctxs[i]->cur;
+    tt[i] = ctxs[i]->t;
+  }
+  // tables of the five stages of one step at host offset base; the
+  // contexts' step state is taken from cur / tt
+  auto build = [&](size_t base, std::vector<Launch>& launches) {
+    size_t off = base;
     for (int i = 0; i < 5; ++i) {
-      const size_t stage_base = off;
-      size_t rec_off = stage_base, tiles_off = stage_base + static_cast<size_t>(n) * rec;
+      size_t rec_off = off, tiles_off = off + static_cast<size_t>(n) * rec;
+      int gi = 0;
       for (auto& g : groups) {
-        Launch L{g.first.first, g.first.second, static_cast<int>(g.second.size()), 0, rec_off, tiles_off};
+        Launch L{g.first.first, g.first.second, static_cast<int>(g.second.size()), 0, gi++, rec_off, tiles_off};
         int32_t* ts = reinterpret_cast<int32_t*>(&host[tiles_off]);
         int tiles = 0;
         for (size_t m = 0; m < g.second.size(); ++m) {
-          ewdg_ctx* c = ctxs[g.second[m]];
-          const double dt = dts[g.second[m]];
-          const int cur = (c->cur + i) & 1;
-          const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, c->t + kRkC[i] * dt);
-          stage_args_fill(c->d, c->d.q[cur], c->d.s[cur], c->d.q[1 - cur], c->d.s[1 - cur], c->d.res, sc,
+          const int k = g.second[m];
+          ewdg_ctx* c = ctxs[k];
+          const double dt = dts[k];
+          const int cs = (cur[k] + i) & 1;
+          const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, tt[k] + kRkC[i] * dt);
+          stage_args_fill(c->d, c->d.q[cs], c->d.s[cs], c->d.q[1 - cs], c->d.s[1 - cs], c->d.res, sc,
                           &host[rec_off]);
           rec_off += rec;
           ts[m] = tiles;
@@ -760,26 +803,82 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
         launches.push_back(L);
         tiles_off += (g.second.size() + 1) * 4;
       }
-      off = (tiles_off + 255) / 256 * 256;
+      off = base + (tiles_off - base + 255) / 256 * 256;
     }
-    hipError_t e = hipMemcpyAsync(dev, host.data(), off, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return ctxs[0]->hip(e, "batch table copy");
-    for (const Launch& L : launches) {
-      e = launch_stage_batch(L.N, L.prec, dev + L.args_off, static_cast<int>(rec),
-                             reinterpret_cast<const int*>(dev + L.tiles_off), L.nreq, L.ntiles, st);
-      if (e != hipSuccess) return ctxs[0]->hip(e, "batched stage");
-    }
+  };
+  auto advance = [&]() {
     for (int i = 0; i < n; ++i) {
-      ewdg_ctx* c = ctxs[i];
-      c->cur = (c->cur + 5) & 1;
-      c->t = c->t + dts[i];
-      if (c->nr > 0) {
-        e = launch_receivers(c->d, c->d.q[c->cur], c->nr, c->rec_count, st);
-        if (e != hipSuccess) return c->hip(e, "receivers");
-        ++c->rec_count;
+      cur[i] = (cur[i] + 5) & 1;
+      tt[i] = tt[i] + dts[i];
+    }
+  };
+  auto commit = [&](int steps_done) {
+    for (int i = 0; i < n; ++i) {
+      ctxs[i]->cur = cur[i];
+      ctxs[i]->t = tt[i];
+      if (ctxs[i]->nr > 0) ctxs[i]->rec_count += steps_done;
+    }
+  };
+  if (!whole) {
+    for (int step = 0; step < nsteps; ++step) {
+      std::vector<Launch> launches;
+      build(0, launches);
+      hipError_t e = hipMemcpyAsync(dev, host.data(), stride, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return ctxs[0]->hip(e, "batch table copy");
+      for (const Launch& L : launches) {
+        e = launch_stage_batch(L.N, L.prec, dev + L.args_off, static_cast<int>(rec),
+                               reinterpret_cast<const int*>(dev + L.tiles_off), L.nreq, L.ntiles, st);
+        if (e != hipSuccess) return ctxs[0]->hip(e, "batched stage");
+      }
+      advance();
+      for (int i = 0; i < n; ++i) {
+        ewdg_ctx* c = ctxs[i];
+        if (c->nr > 0) {
+          e = launch_receivers(c->d, c->d.q[cur[i]], c->nr, c->rec_count, st);
+          if (e != hipSuccess) return c->hip(e, "receivers");
+        }
+      }
+      commit(1);
+    }
+    return EWDG_OK;
+  }
+  std::vector<std::vector<Launch>> launches(nsteps);
+  std::vector<std::vector<int>> cur_after(nsteps);
+  for (int step = 0; step < nsteps; ++step) {
+    build(static_cast<size_t>(step) * stride, launches[step]);
+    advance();
+    cur_after[step] = cur;
+  }
+  hipError_t e = hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return ctxs[0]->hip(e, "batch table copy");
+  BatchStreams& bs = batch_streams();
+  if (!bs.fork) return ctxs[0]->fail(EWDG_EHIP, "could not create the batch fork event");
+  if ((e = hipEventRecord(bs.fork, st)) != hipSuccess) return ctxs[0]->hip(e, "event");
+  int gi = 0;
+  for (auto& g : groups) {
+    GroupStream* gs = bs.get(g.first.first, g.first.second);
+    if (!gs) return ctxs[0]->fail(EWDG_EHIP, "could not create a batch stream");
+    if ((e = hipStreamWaitEvent(gs->s, bs.fork, 0)) != hipSuccess) return ctxs[0]->hip(e, "event wait");
+    for (int step = 0; step < nsteps; ++step) {
+      for (const Launch& L : launches[step]) {
+        if (L.group != gi) continue;
+        e = launch_stage_batch(L.N, L.prec, dev + L.args_off, static_cast<int>(rec),
+                               reinterpret_cast<const int*>(dev + L.tiles_off), L.nreq, L.ntiles, gs->s);
+        if (e != hipSuccess) return ctxs[0]->hip(e, "batched stage");
+      }
+      for (int k : g.second) {
+        ewdg_ctx* c = ctxs[k];
+        if (c->nr > 0) {
+          e = launch_receivers(c->d, c->d.q[cur_after[step][k]], c->nr, c->rec_count + step, gs->s);
+          if (e != hipSuccess) return c->hip(e, "receivers");
+        }
       }
     }
+    if ((e = hipEventRecord(gs->done, gs->s)) != hipSuccess) return ctxs[0]->hip(e, "event");
+    if ((e = hipStreamWaitEvent(st, gs->done, 0)) != hipSuccess) return ctxs[0]->hip(e, "event wait");
+    ++gi;
   }
+  commit(nsteps);
   return EWDG_OK;
 }
 

@@ -123,7 +123,10 @@ class Server:
         self.stream = torch.cuda.Stream()          # chunks
         self.setup_stream = torch.cuda.Stream()    # admissions
         self.pool = ThreadPoolExecutor(max_workers=int(prep_workers))
-        self.table = torch.empty(B.batch_table_bytes(self.slots), dtype=torch.uint8, device="cuda")
+        # room for the tables of a whole chunk: one upload per chunk, and each
+        # degree class runs on a stream of its own
+        per_step = (B.batch_table_bytes(self.slots) + 255) // 256 * 256
+        self.table = torch.empty(per_step * self.chunk, dtype=torch.uint8, device="cuda")
 
     def close(self):
         self.pool.shutdown(wait=True)

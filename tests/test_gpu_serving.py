@@ -26,8 +26,12 @@ def _solo(req, precision, nsteps):
     return c.get_state().cpu().numpy(), c
 
 
+@pytest.mark.parametrize("whole", [False, True])
 @pytest.mark.parametrize("precision", [32, 64])
-def test_step_batch_equals_solo(precision):
+def test_step_batch_equals_solo(precision, whole):
+    """whole=False: a one-step table (one upload per step, one stream);
+    whole=True: room for every step's table (one upload, a stream per
+    degree class)."""
     import paper_1711_01175_amd as P
     reqs = request_stream(5, n_range=(3, 5), degrees=(2, 3, 4, 5), nsteps=12, seed0=40)
     solo = [_solo(r, precision, 12)[0] for r in reqs]
@@ -40,7 +44,9 @@ def test_step_batch_equals_solo(precision):
         c.set_source(r.xs, r.direction, 1.0, r.f0, r.t0)
         ctxs.append(c)
         dts.append(c.cfl_dt(0.5))
-    table = torch.empty(P.batch_table_bytes(len(ctxs)), dtype=torch.uint8, device="cuda")
+    per_step = P.batch_table_bytes(len(ctxs))
+    size = (per_step + 255) // 256 * 256 * 7 if whole else per_step
+    table = torch.empty(size, dtype=torch.uint8, device="cuda")
     P.step_batch(ctxs, dts, 5, table)
     P.step_batch(ctxs, dts, 7, table)
     torch.cuda.synchronize()
