@@ -701,14 +701,42 @@ struct GroupStream {
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
 };
+// Two pinned host staging buffers for the whole-chunk tables, used in turn;
+// a buffer is refilled only after its previous upload has executed, so the
+// upload never blocks the host and the caller can queue the next chunk
+// while the device still runs the previous one.
+struct Staging {
+  char* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+};
 struct BatchStreams {
   hipEvent_t fork = nullptr;
   std::map<std::pair<int, int>, GroupStream> g;
+  Staging stage[2];
+  int next = 0;
   GroupStream* get(int N, int prec) {
     GroupStream& x = g[{N, prec}];
     if (!x.s && hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
     if (!x.done && hipEventCreateWithFlags(&x.done, hipEventDisableTiming) != hipSuccess) return nullptr;
     return &x;
+  }
+  // a free staging buffer of at least bytes (waits for its last upload)
+  Staging* staging(size_t bytes) {
+    Staging& b = stage[next];
+    next ^= 1;
+    if (b.pending && hipEventSynchronize(b.copied) != hipSuccess) return nullptr;
+    b.pending = false;
+    if (!b.copied && hipEventCreateWithFlags(&b.copied, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (b.cap < bytes) {
+      if (b.p) (void)hipHostFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+      if (hipHostMalloc(reinterpret_cast<void**>(&b.p), bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+      b.cap = bytes;
+    }
+    return &b;
   }
 };
 BatchStreams& batch_streams() {
@@ -849,10 +877,15 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
     advance();
     cur_after[step] = cur;
   }
-  hipError_t e = hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return ctxs[0]->hip(e, "batch table copy");
   BatchStreams& bs = batch_streams();
   if (!bs.fork) return ctxs[0]->fail(EWDG_EHIP, "could not create the batch fork event");
+  Staging* sb = bs.staging(host.size());
+  if (!sb) return ctxs[0]->fail(EWDG_EHIP, "could not get a pinned staging buffer for the batch tables");
+  std::memcpy(sb->p, host.data(), host.size());
+  hipError_t e = hipMemcpyAsync(dev, sb->p, host.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return ctxs[0]->hip(e, "batch table copy");
+  if ((e = hipEventRecord(sb->copied, st)) != hipSuccess) return ctxs[0]->hip(e, "event");
+  sb->pending = true;
   if ((e = hipEventRecord(bs.fork, st)) != hipSuccess) return ctxs[0]->hip(e, "event");
   int gi = 0;
   for (auto& g : groups) {

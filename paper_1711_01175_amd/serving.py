@@ -11,7 +11,8 @@ request's arithmetic is identical to a solo run, so results do not depend on
 the mix.
 
 Host preparation of arrived requests (worker threads) and device setup of
-admitted ones (a side stream) overlap the running chunk.
+admitted ones (a side stream) overlap the running chunk, and chunks are
+queued two deep so the device does not wait for the host between them.
 
 Only orchestration lives here; every step of the method runs in libewdg.
 """
@@ -53,7 +54,8 @@ class _Live:
     ctx: object
     footprint: int
     dt: float = 0.0
-    done: int = 0
+    done: int = 0        # steps completed on the device
+    sched: int = 0       # steps queued (done plus those of chunks in flight)
     t_admit: float = 0.0
     ws: object = None
     material: object = None
@@ -122,6 +124,7 @@ class Server:
         self.keep_state = keep_state
         self.stream = torch.cuda.Stream()          # chunks
         self.setup_stream = torch.cuda.Stream()    # admissions
+        self.retire_stream = torch.cuda.Stream()   # read-back of finished requests
         self.pool = ThreadPoolExecutor(max_workers=int(prep_workers))
         # room for the tables of a whole chunk: one upload per chunk, and each
         # degree class runs on a stream of its own
@@ -158,6 +161,9 @@ class Server:
 
     def _finish(self, live, now, stats):
         req, ctx = live.req, live.ctx
+        # the request's last chunk is complete; read back on a stream of its
+        # own so the read-back does not wait for the chunk queued after it
+        ctx.set_stream(self.retire_stream.cuda_stream)
         traces = ctx.receivers() if len(req.receivers) else np.zeros((0, 0, 3))
         state = ctx.get_state().cpu().numpy() if self.keep_state else None
         stats.results.append(Result(req.rid, req.arrival, live.t_admit, now, now - req.arrival, ctx.K,
@@ -169,24 +175,36 @@ class Server:
     def run(self, requests, clock=time.perf_counter, sleep=time.sleep, progress=None):
         """Serve requests arriving at req.arrival seconds after the start.
 
+        Chunks are pipelined two deep: the next chunk of every running
+        request is queued behind the one on the device before the host
+        waits for the older one, so admissions and read-back overlap device
+        work and the device does not idle between chunks.
+
         progress: optional callable(done, total, elapsed_s) called whenever
         requests complete."""
+        torch = self.torch
         stats = ServeStats()
         total = len(requests)
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         waiting, active = deque(), []      # waiting: futures of prepared requests, FIFO
+        inflight = deque()                 # (event, requests, steps) per queued chunk
         used = 0
         t0 = clock()
-        while pending or waiting or active:
+        while pending or waiting or active or inflight:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(self.pool.submit(self._prepare, pending.popleft()))
-            # launch the next chunk of everything active, then do host work
-            chunk = 0
-            if active:
-                chunk = min(self.chunk, min(a.req.nsteps - a.done for a in active))
-                B.step_batch([a.ctx for a in active], [a.dt for a in active], chunk, self.table,
+            # queue the next chunk of every request with steps left to queue
+            launch = [a for a in active if a.sched < a.req.nsteps]
+            if launch and len(inflight) < 2:
+                chunk = min(self.chunk, min(a.req.nsteps - a.sched for a in launch))
+                B.step_batch([a.ctx for a in launch], [a.dt for a in launch], chunk, self.table,
                              self.stream.cuda_stream)
+                ev = torch.cuda.Event()
+                ev.record(self.stream)
+                for a in launch:
+                    a.sched += chunk
+                inflight.append((ev, launch, chunk))
             # admission in arrival order among prepared requests (the head of
             # the queue blocks the ones behind it until it is prepared)
             ready = []
@@ -209,25 +227,32 @@ class Server:
                     break
             for _ in range(sum(1 for w in ready if id(w) in rej or id(w) in adm)):
                 waiting.popleft()
+            for w in admitted:
+                if w.req.nsteps <= 0:          # nothing to run: retire at once
+                    self._finish(w, clock() - t0, stats)
+                    used -= w.footprint
+                else:
+                    active.append(w)
             stats.max_used_bytes = max(stats.max_used_bytes, used)
-            if chunk:
-                self.stream.synchronize()
+            stats.max_active = max(stats.max_active, len(active))
+            # wait for the oldest chunk once another is queued behind it (or
+            # nothing more can be queued), then retire what it completed
+            more = any(a.sched < a.req.nsteps for a in active)
+            if inflight and (len(inflight) >= 2 or not more):
+                ev, lives, chunk = inflight.popleft()
+                ev.synchronize()
                 now = clock() - t0
-                still, finished = [], 0
-                for a in active:
+                finished = 0
+                for a in lives:
                     a.done += chunk
                     if a.done >= a.req.nsteps:
                         self._finish(a, now, stats)
                         used -= a.footprint
+                        active.remove(a)
                         finished += 1
-                    else:
-                        still.append(a)
-                active = still
                 if finished and progress is not None:
                     progress(len(stats.results), total, now)
-            active += admitted
-            stats.max_active = max(stats.max_active, len(active))
-            if not active and not admitted:
+            elif not inflight and not active:
                 if waiting:
                     sleep(0.001)
                 elif pending:
