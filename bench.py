@@ -68,6 +68,39 @@ def algorithmic_bytes_per_element(Np, Nq, b):
     return 36 * Np * b + Np * Np * b + 2 * Nq * b + 26 * b + 48
 
 
+def flops_per_element(Np, Nfp, Nq):
+    """Flops per element per stage: volume 36 Np^2 (18 reference products),
+    stress projection 24 Nq Np + 10 Nq, lift 72 Np Nfp, mass inverse 6 Np^2,
+    interface flux about 480 Nfp, LSRK update 36 Np."""
+    return 36 * Np * Np + 24 * Nq * Np + 10 * Nq + 72 * Np * Nfp + 6 * Np * Np + 480 * Nfp + 36 * Np
+
+
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {32: 157.3, 64: 78.6}   # MI355X dense FP32 / FP64 matrix
+
+
+def sweep_degrees(steps=10, warmup=2):
+    """Stage time per degree on the workload meshes of each degree (N=3, 4:
+    32^3 x 6 tets; N=5: 24^3 x 6; N=7: 16^3 x 6), both precisions, with the
+    HBM and matrix-core roofline fractions of the algorithmic work."""
+    out = {"sweep": "degrees", "steps": steps, "rows": []}
+    for N, n in ((3, 32), (4, 32), (5, 24), (7, 16)):
+        EToV, VXYZ, _ = build_workload(n, N)
+        for prec in (32, 64):
+            r = run_gpu(prec, N, n, steps, warmup, EToV, VXYZ)
+            K, Np, Nq = r["K"], r["Np"], r["Nq"]
+            Nfp = (N + 1) * (N + 2) // 2
+            s = r["ms"] * 1e-3 / (5 * steps)
+            b = algorithmic_bytes_per_element(Np, Nq, prec // 8) * K
+            f = flops_per_element(Np, Nfp, Nq) * K
+            out["rows"].append({"N": N, "K": K, "prec": prec, "stage_us": round(s * 1e6, 1),
+                                "GDOF_per_s": round(K * Np * 9 / s / 1e9, 2),
+                                "hbm_frac": round(b / s / 1e9 / PEAK_HBM_GBS, 3),
+                                "mfma_frac": round(f / s / 1e12 / PEAK_TFLOPS[prec], 3)})
+            print(json.dumps(out["rows"][-1]), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def build_workload(n, N):
     from workloads import media
     from workloads.mesh import kuhn_periodic_mesh
@@ -305,6 +338,8 @@ def main():
                     help="run only the FP32 adjoint leg and print its JSON (for profiling)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="time a plain device copy of 2 GiB instead (HBM calibration)")
+    ap.add_argument("--sweep-degrees", action="store_true",
+                    help="time the stage at N=3, 4, 5, 7 in both precisions instead (one JSON line)")
     ap.add_argument("--probe-bandwidth", action="store_true",
                     help="time plain torch kernels on 4 GiB tensors instead (achievable HBM rates)")
     args = ap.parse_args()
@@ -319,6 +354,9 @@ def main():
         return
     if args.probe_bandwidth:
         probe_bandwidth()
+        return
+    if args.sweep_degrees:
+        sweep_degrees()
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": run_adjoint(check_fp64=False)}), flush=True)
