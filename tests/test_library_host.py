@@ -181,3 +181,5 @@ def test_empty_batch_and_null_arguments():
     c.set_mesh(EToV, VXYZ)
     assert lib.ewdg_workspace_bytes(c.h, -1, 0, ctypes.byref(size)) == B.EWDG_EINVAL
     assert lib.ewdg_adjoint_workspace_bytes(c.h, 10, 5, ctypes.byref(size)) == B.EWDG_ESTATE  # not bound
+    assert lib.ewdg_adjoint_workspace_bytes_overlapped(c.h, 10, 5, ctypes.byref(size)) == B.EWDG_ESTATE
+    assert lib.ewdg_adjoint_workspace_bytes_overlapped(None, 10, 5, ctypes.byref(size)) != B.EWDG_OK
