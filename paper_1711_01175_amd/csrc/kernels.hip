@@ -103,6 +103,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   const int e0 = tile * E;
   const bool own = w < RT;             // this wave owns node row tile R = w
   const int R = w;
+  // Bank swizzle of the 16-element column groups in the buffers of row
+  // stride SV and SF (both 16 mod 32 values): the element slot of row r is
+  // e ^ (r mod 16).  The matrix-core reads (lanes over the elements of a few
+  // rows) stay conflict-free, and the element-wise accesses (lanes over
+  // rows, one element) no longer fall into one or two banks.
+  auto sw = [](int r) { return r & 15; };
   // own stresses [Np][SE] beside the face buffer, from the first volume
   // direction until the last flux, when they fit in the Y region
   constexpr bool SIGL = NfpK * SF + Np * SE <= TL::Y;
@@ -156,7 +162,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     const int e = x / (3 * Np), rem = x % (3 * Np), c = rem / Np, j = rem % Np;
     const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
     const T v = a.qin[ge * 9 * Np + c * Np + j];
-    Sv[j * SV + c * 16 + e] = (e0 + e < Ke) ? v : T(0);
+    Sv[j * SV + c * 16 + (e ^ sw(j))] = (e0 + e < Ke) ? v : T(0);
   }
   for (int x = tid; x < (NpK - Np) * SV; x += NT) {
     Sv[Np * SV + x] = T(0);
@@ -202,9 +208,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         }
         const T* g = &sgeo[e * 32 + k * 3];
         // rows of sigma in Voigt order xx,yy,zz,yz,xz,xy
-        SG[j * SV + 0 * 16 + e] = g[0] * sg[0] + g[1] * sg[5] + g[2] * sg[4];
-        SG[j * SV + 1 * 16 + e] = g[0] * sg[5] + g[1] * sg[1] + g[2] * sg[3];
-        SG[j * SV + 2 * 16 + e] = g[0] * sg[4] + g[1] * sg[3] + g[2] * sg[2];
+        const int es = e ^ sw(j);
+        SG[j * SV + 0 * 16 + es] = g[0] * sg[0] + g[1] * sg[5] + g[2] * sg[4];
+        SG[j * SV + 1 * 16 + es] = g[0] * sg[5] + g[1] * sg[1] + g[2] * sg[3];
+        SG[j * SV + 2 * 16 + es] = g[0] * sg[4] + g[1] * sg[3] + g[2] * sg[2];
       }
     }
     __syncthreads();
@@ -214,7 +221,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       for (int c = 0; c < 3; ++c) gv[c] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < KD; ++kk) {
-        const int row = (4 * kk + lg) * SV + lr;
+        const int rr = 4 * kk + lg;
+        const int row = rr * SV + (lr ^ sw(rr));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           rhs[c] = M::mma(af[kk], SG[row + c * 16], rhs[c]);
@@ -252,7 +260,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const int x = tid + p * NT;
       if (x >= Nfp * E) continue;
       const int e = x / Nfp, j = x % Nfp;
-      T* fl = &Sf[j * SF + e];
+      T* fl = &Sf[j * SF + (e ^ sw(j))];
       if (e0 + e >= Ke) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) fl[c * 16] = T(0);
@@ -264,7 +272,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const T fs = gg[9 + f * 4 + 3];
       T vm[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) vm[c] = Sv[il * SV + c * 16 + e];
+      for (int c = 0; c < 3; ++c) vm[c] = Sv[il * SV + c * 16 + (e ^ sw(il))];
       T smv[6];
 #pragma unroll
       for (int m = 0; m < 6; ++m) smv[m] = SIGL ? Ssig[il * SE + m * 16 + e] : pf[p].sm[m];
@@ -291,7 +299,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     if (own) {
 #pragma unroll
       for (int kk = 0; kk < KF; ++kk) {
-        const int row = (4 * kk + lg) * SF + lr;
+        const int rr = 4 * kk + lg;
+        const int row = rr * SF + (lr ^ sw(rr));
 #pragma unroll
         for (int c = 0; c < 9; ++c) rhs[c] = M::mma(lf[kk], Sf[row + c * 16], rhs[c]);
       }
@@ -316,7 +325,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const int x = tid + p * NT;
       const int e = x / Np, i = x % Np;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) vold[p][c] = x < E * Np ? Sv[i * SV + c * 16 + e] : T(0);
+      for (int c = 0; c < 3; ++c) vold[p][c] = x < E * Np ? Sv[i * SV + c * 16 + (e ^ sw(i))] : T(0);
     }
   }
   if (own) {
@@ -325,7 +334,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const int i = R * 16 + M::row(lg, r);
       if (i < NpK) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Srv[i * SV + c * 16 + lr] = rhs[c][r];
+        for (int c = 0; c < 3; ++c) Srv[i * SV + c * 16 + (lr ^ sw(i))] = rhs[c][r];
 #pragma unroll
         for (int m = 0; m < 6; ++m) Ser[i * SE + m * 16 + lr] = rhs[3 + m][r];
       }
@@ -370,9 +379,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       for (int u = 0; u < CW; ++u) {
         if (j0 + u < Np) {
           const int j = j0 + u;
-          o[0] += w[u] * Srv[j * SV + e];
-          o[1] += w[u] * Srv[j * SV + 16 + e];
-          o[2] += w[u] * Srv[j * SV + 32 + e];
+          const int es = e ^ sw(j);
+          o[0] += w[u] * Srv[j * SV + es];
+          o[1] += w[u] * Srv[j * SV + 16 + es];
+          o[2] += w[u] * Srv[j * SV + 32 + es];
         }
       }
     }
