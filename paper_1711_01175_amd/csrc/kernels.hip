@@ -107,8 +107,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // stride SV and SF (both 16 mod 32 values): the element slot of row r is
   // e ^ (r mod 16).  The matrix-core reads (lanes over the elements of a few
   // rows) stay conflict-free, and the element-wise accesses (lanes over
-  // rows, one element) no longer fall into one or two banks.
-  auto sw = [](int r) { return r & 15; };
+  // rows, one element) no longer fall into one or two banks.  N = 7 keeps
+  // the plain layout: there the extra index arithmetic raises the register
+  // spills (140 -> 252 bytes per lane) and costs 11 %.
+  auto sw = [](int r) { return N < 7 ? (r & 15) : 0; };
   // own stresses [Np][SE] beside the face buffer, from the first volume
   // direction until the last flux, when they fit in the Y region
   constexpr bool SIGL = NfpK * SF + Np * SE <= TL::Y;
