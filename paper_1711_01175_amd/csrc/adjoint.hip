@@ -522,12 +522,15 @@ __global__ __launch_bounds__((Tile<N>::NT), EWDG_ADJ_OCC) void k_adjB_mma(AdjArg
   }
   T* Sv = r1;               // [NpK][SV] ytil_c at column c*16+e
   T* SG = r1 + NpK * SV;    // [NpK][SV] z_c^k for the current direction
+  // bank swizzle of the element slots of Sv and SG as in the stage kernel:
+  // element e of row r sits in slot e ^ (r mod 16) (not at N = 7)
+  auto sw = [](int r) { return N < 7 ? (r & 15) : 0; };
   for (int x = tid; x < E * 3 * NpK; x += NT) {
     const int e = x / (3 * NpK), rem = x % (3 * NpK), c = rem / NpK, j = rem % NpK;
     T v = T(0);
     if (e < ne && j < Np) v = a.ytil[(e0 + e) * 3 * Np + c * Np + j];
-    Sv[j * SV + c * 16 + e] = v;
-    if (j >= Np) SG[j * SV + c * 16 + e] = T(0);
+    Sv[j * SV + c * 16 + (e ^ sw(j))] = v;
+    if (j >= Np) SG[j * SV + c * 16 + (e ^ sw(j))] = T(0);
   }
   __syncthreads();
 
@@ -564,9 +567,10 @@ __global__ __launch_bounds__((Tile<N>::NT), EWDG_ADJ_OCC) void k_adjB_mma(AdjArg
         const T* y6 = yr[p];
         const T* g = &sgeo[e * 32 + k * 3];
         // z_c = sum_m g_m ybar_cm, ybar the strain adjoint as a tensor (off-diagonal halves)
-        SG[r * SV + 0 * 16 + e] = g[0] * y6[0] + T(0.5) * (g[1] * y6[5] + g[2] * y6[4]);
-        SG[r * SV + 1 * 16 + e] = g[1] * y6[1] + T(0.5) * (g[0] * y6[5] + g[2] * y6[3]);
-        SG[r * SV + 2 * 16 + e] = g[2] * y6[2] + T(0.5) * (g[0] * y6[4] + g[1] * y6[3]);
+        const int es = e ^ sw(r);
+        SG[r * SV + 0 * 16 + es] = g[0] * y6[0] + T(0.5) * (g[1] * y6[5] + g[2] * y6[4]);
+        SG[r * SV + 1 * 16 + es] = g[1] * y6[1] + T(0.5) * (g[0] * y6[5] + g[2] * y6[3]);
+        SG[r * SV + 2 * 16 + es] = g[2] * y6[2] + T(0.5) * (g[0] * y6[4] + g[1] * y6[3]);
       }
     }
     __syncthreads();
@@ -576,7 +580,8 @@ __global__ __launch_bounds__((Tile<N>::NT), EWDG_ADJ_OCC) void k_adjB_mma(AdjArg
       for (int c = 0; c < 3; ++c) gb[c] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < KD; ++kk) {
-        const int row = (4 * kk + lg) * SV + lr;
+        const int rr = 4 * kk + lg;
+        const int row = rr * SV + (lr ^ sw(rr));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           gb[c] = M::mma(af[kk], Sv[row + c * 16], gb[c]);
