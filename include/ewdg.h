@@ -37,11 +37,14 @@
  * negative EWDG_E* code) and never throws.  ewdg_last_error(ctx) returns a
  * message owned by the context, valid until its next call.  A context is
  * not thread-safe; distinct contexts are independent.  All device work is
- * enqueued on the context's HIP stream; functions returning host data
+ * enqueued on the context's HIP stream (ewdg_step_batch and the overlapped
+ * adjoint sweep also use streams of the library's own, forked from and
+ * joined back into the caller's stream); functions returning host data
  * synchronise that stream.  Host input arrays are borrowed for the call and
  * copied.  Device memory is owned by the caller: the library works inside
- * one caller-allocated workspace (ewdg_workspace_bytes / ewdg_bind_workspace)
- * and never allocates device memory itself.
+ * caller-allocated workspaces (ewdg_workspace_bytes / ewdg_bind_workspace,
+ * and the adjoint's) and never allocates device memory itself; it keeps two
+ * pinned host staging buffers for the batch tables.
  */
 #ifndef EWDG_H
 #define EWDG_H
