@@ -344,8 +344,7 @@ def main():
                     help="time plain torch kernels on 4 GiB tensors instead (achievable HBM rates)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
-              "(the design notes describe how the path would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
