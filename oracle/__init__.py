@@ -5,10 +5,11 @@ benchmark's CPU-baseline leg may import this package.  The HIP library and
 its Python binding never import it, and this package imports nothing from
 them: the two share no kernels, helpers, tables or constants.
 
-The oracle is written for clarity, not speed: a modal Galerkin method with an
-orthonormal basis of P_N built by Cholesky orthonormalisation of Legendre
-products, every integral evaluated by quadrature, faces matched by physical
-coordinates.  The GPU path instead uses a nodal basis, derivative/lift
+The oracle is written for clarity, not speed: a modal Galerkin method with the
+orthonormal Dubiner (Proriol-Koornwinder) basis of P_N, built from Jacobi
+polynomials in collapsed coordinates (values from scipy.special.eval_jacobi),
+every integral evaluated by quadrature (Gauss-Jacobi nodes from
+scipy.special.roots_jacobi), faces matched by physical coordinates.  The GPU path instead uses a nodal basis, derivative/lift
 matrices and topological face permutations.  Both discretise the same
 semi-discrete operator, which does not depend on the basis:
 
@@ -23,7 +24,8 @@ semi-discrete operator, which does not depend on the basis:
 
 Parity status: every function is pinned by tests under tests/ (exactness,
 closed-form energy rate, conservation, plane-wave convergence, symmetry,
-Runge-Kutta order conditions).  Absolute solution values of the large
+Runge-Kutta order conditions, receiver sampling time against an exact
+wave).  Absolute solution values of the large
 heterogeneous workloads are not printed in the paper and are pinned only
 through those properties.
 """

@@ -17,7 +17,7 @@ def _random_state(op, seed):
     return np.random.default_rng(seed).standard_normal((op.K, 9, op.Np))
 
 
-@pytest.mark.parametrize("N,n", [(1, 3), (2, 3), (3, 3)])
+@pytest.mark.parametrize("N,n", [(1, 3), (2, 3), (3, 3), (4, 3), (7, 3)])
 def test_energy_rate_equals_face_dissipation(N, n):
     """dE/dt = -sum_faces int sum_modes ([T]^2 + Z^-Z^+[v]^2)/(Z^-+Z^+),
     derived by hand from the interface states; holds for any state and any
@@ -65,30 +65,44 @@ def test_constant_states_are_steady():
     assert np.abs(op2.rhs(c2)).max() < 1e-12
 
 
-def test_polynomial_states_give_the_pde_operator():
-    """A global quadratic state is continuous, so away from the periodic seam
-    every jump vanishes and L equals the PDE operator exactly."""
-    N, n = 3, 4
+def _monomials(deg, count, rng):
+    """count distinct exponent triples (a, b, c) with a + b + c <= deg,
+    always including every monomial of total degree exactly deg along one
+    axis so that the top degree is exercised."""
+    allm = [(a, b, c) for a in range(deg + 1) for b in range(deg + 1 - a) for c in range(deg + 1 - a - b)]
+    pick = [allm[i] for i in rng.choice(len(allm), size=min(count, len(allm)), replace=False)]
+    for top in ((deg, 0, 0), (0, deg, 0), (0, 0, deg), (deg - 1, 1, 0) if deg > 1 else (1, 0, 0)):
+        if top not in pick:
+            pick.append(top)
+    return pick
+
+
+@pytest.mark.parametrize("N,deg", [(3, 2), (3, 3), (4, 4), (7, 7)])
+def test_polynomial_states_give_the_pde_operator(N, deg):
+    """A global polynomial state of degree <= N is continuous, so away from
+    the periodic seam every jump vanishes and L equals the PDE operator
+    exactly (the derivatives of a degree-N polynomial are exact on P_N)."""
+    n = 4
     op, EToV, VXYZ, xyz, (rho, lam, mu) = oracle_case(N, n, medium="homogeneous")
-    rng = np.random.default_rng(8)
-    Cq = rng.standard_normal((9, 10))          # quadratic in x,y,z per field
+    rng = np.random.default_rng(8 + N + deg)
+    mons = _monomials(deg, 8, rng)
+    Cq = rng.standard_normal((9, len(mons)))
 
-    def basis(x):
-        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
-        return np.stack([np.ones_like(X), X, Y, Z, X * X, Y * Y, Z * Z, X * Y, X * Z, Y * Z], -1)
-
-    def dbasis(x, k):
-        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
-        o, z = np.ones_like(X), np.zeros_like(X)
-        d = [[z, o, z, z, 2 * X, z, z, Y, Z, z],
-             [z, z, o, z, z, 2 * Y, z, X, z, Z],
-             [z, z, z, o, z, z, 2 * Z, z, X, Y]][k]
-        return np.stack(d, -1)
+    def basis(x, dk=None):
+        cols = []
+        for (a, b, c) in mons:
+            e = [a, b, c]
+            coef = 1.0
+            if dk is not None:
+                coef = e[dk]
+                e[dk] = max(e[dk] - 1, 0)
+            cols.append(coef * x[..., 0] ** e[0] * x[..., 1] ** e[1] * x[..., 2] ** e[2])
+        return np.stack(cols, -1)
 
     fields = np.einsum('kqb,fb->kfq', basis(xyz), Cq)
     c = op.project_q(fields)
     L = op.rhs(c)
-    grads = np.stack([np.einsum('kqb,fb->kfq', dbasis(xyz, k), Cq) for k in range(3)], 2)
+    grads = np.stack([np.einsum('kqb,fb->kfq', basis(xyz, k), Cq) for k in range(3)], 2)
     # exact: v_t = div(C e) / rho, e_t = sym grad v (rho = lambda = mu = 1)
     de = grads[:, 3:9]                          # d_k e_m
     dtr = de[:, 0] + de[:, 1] + de[:, 2]        # [K][3 dir][Nq]
@@ -107,6 +121,9 @@ def test_polynomial_states_give_the_pde_operator():
     interior = np.all(np.abs(VXYZ) < 1 - 1e-12, axis=(1, 2))
     assert interior.sum() > 0
     err = np.abs(L[interior] - exact[interior]).max()
+    # at the seam the polynomial jumps, so some boundary element must differ
+    # (the check is not vacuous)
+    assert np.abs(L[~interior] - exact[~interior]).max() > 1e-6 * np.abs(exact).max()
     assert err < 1e-11 * np.abs(exact).max()
 
 

@@ -96,3 +96,39 @@ def test_cfl_dt_closed_form():
     expect = 0.5 * (h / (2 * (1 + np.sqrt(2)))) / np.sqrt(3.0) / 16
     assert abs(timestep.cfl_dt(op, 0.5) - expect) < 1e-16
     assert abs(expect - 1.868e-3) < 1e-6
+
+
+def test_receivers_sampled_after_each_full_step():
+    """Receiver n holds v(x_r) at t_{n+1} = t0 + (n+1) dt, after the n-th
+    full step (not at a stage time, not before the update).  Pinned to the
+    exact P-plane wave: the discretisation error at the receivers is far
+    below the change of v over one step, so sampling one step early (the
+    state before the update) or one step late fails."""
+    N, n, steps = 3, 4, 20
+    op, EToV, VXYZ, xyz, _ = oracle_case(N, n, medium="homogeneous")
+    cp, k = np.sqrt(3.0), np.pi
+
+    def wave(x, t):
+        ph = k * (x[..., 0] - cp * t)
+        out = np.zeros(x.shape[:-1] + (9,))
+        out[..., 0] = np.cos(ph)
+        out[..., 3] = -np.cos(ph) / cp
+        return out
+
+    rec = np.array([[0.13, -0.41, 0.27], [-0.62, 0.35, -0.08], [0.71, 0.52, 0.66]])
+    dt = timestep.cfl_dt(op, 0.5)
+    t_start = 0.05
+    c0 = op.project_q(np.moveaxis(wave(xyz, t_start), -1, 1))
+    cT, T, traces = timestep.run(op, c0, dt, steps, t=t_start, receivers=rec)
+    assert traces.shape == (steps, len(rec), 3)
+    times = t_start + dt * np.arange(1, steps + 1)
+    exact = np.stack([wave(rec, t)[:, 0:3] for t in times])            # [steps][nr][3]
+    early = np.stack([wave(rec, t - dt)[:, 0:3] for t in times])
+    late = np.stack([wave(rec, t + dt)[:, 0:3] for t in times])
+    err = np.abs(traces - exact).max()
+    assert err < 2e-3
+    assert np.abs(traces - early).max() > 5 * err
+    assert np.abs(traces - late).max() > 5 * err
+    # the last record is the value of the final state at the receivers
+    assert np.abs(traces[-1] - op.eval_points(cT, rec)[:, 0:3]).max() < 1e-14
+    assert abs(T - times[-1]) < 1e-14
