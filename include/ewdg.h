@@ -157,8 +157,12 @@ int ewdg_rhs(ewdg_ctx* ctx, double t, const void* q_dev, void* rhs_dev);
 int ewdg_step(ewdg_ctx* ctx, double dt, int nsteps);
 /* Current simulation time. */
 int ewdg_time(const ewdg_ctx* ctx, double* t);
-/* E = 1/2 (rho v, v)_Q + 1/2 sum_K J sum_q w e:sigma, accumulated in FP64
- * with a deterministic reduction; synchronises. */
+/* The energy of the stored state in the material-weighted norms of Sec. 2
+ * (the (rho v, v) inner product and the elastic one of sigma = C e),
+ * evaluated with the quadrature Q_N:
+ *   E = 1/2 (rho v, v)_Q + 1/2 sum_K J sum_q w e:sigma,
+ * the quantity the upwind flux makes non-increasing in time.  Accumulated
+ * in FP64 with a deterministic reduction; synchronises. */
 int ewdg_energy(ewdg_ctx* ctx, double* E);
 
 /* Batched stepping of many independent contexts (continuous-batching

@@ -82,9 +82,12 @@ class Basis:
                           P_k^(2i+2j+2,0)(c) (1-c)^(i+j),   i+j+k <= N,
     with P^(alpha,beta) the Jacobi polynomials normalised to unit norm under
     their weight.  Jacobi values come from scipy.special.eval_jacobi.  The
-    collapsed map is singular on the edge s+t=0 and at t=1; the oracle only
-    evaluates at quadrature points, face-rule points and user points strictly
-    inside the element's faces or volume, where it is smooth.
+    collapsed map is singular on the edge s+t=0 and at the vertex t=1.  For
+    values the singularity is removable: on s+t=0 the factor (1-b)^i is zero
+    for i > 0 and P_0 is constant, so any a gives the same value (a = -1 is
+    taken); at t=1 likewise (1-c)^(i+j) vanishes unless i = j = 0 (b = -1 is
+    taken).  Gradients are only asked for away from that edge (quadrature
+    and face-rule points), and there the map is smooth.
     """
 
     def __init__(self, N):
@@ -109,19 +112,21 @@ class Basis:
         return p, dp
 
     @staticmethod
-    def _collapse(x):
+    def _collapse(x, singular_ok=False):
         r, s, t = x[:, 0], x[:, 1], x[:, 2]
         den_a = -s - t
         den_b = 1.0 - t
-        if np.any(den_a <= 1e-12) or np.any(den_b <= 1e-12):
+        sa = den_a <= 1e-12
+        sb = den_b <= 1e-12
+        if not singular_ok and (np.any(sa) or np.any(sb)):
             raise ValueError("point on the singular edge of the collapsed map")
-        a = 2.0 * (1.0 + r) / den_a - 1.0
-        b = 2.0 * (1.0 + s) / den_b - 1.0
+        a = np.where(sa, -1.0, 2.0 * (1.0 + r) / np.where(sa, 1.0, den_a) - 1.0)
+        b = np.where(sb, -1.0, 2.0 * (1.0 + s) / np.where(sb, 1.0, den_b) - 1.0)
         return r, s, t, a, b, t.copy(), den_a, den_b
 
     def _eval(self, x, grad):
         x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
-        r, s, t, a, b, c, den_a, den_b = self._collapse(x)
+        r, s, t, a, b, c, den_a, den_b = self._collapse(x, singular_ok=not grad)
         n = x.shape[0]
         P = np.empty((n, self.Np))
         if grad:

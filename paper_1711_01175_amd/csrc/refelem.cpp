@@ -1,5 +1,16 @@
 // Reference tetrahedron: warp & blend nodes, Dubiner basis, Stroud
 // quadrature and the dense reference operators (FP64, host).
+//
+// Published methods followed here, each written from its description:
+//  * the orthonormal Jacobi polynomials by their three-term recurrence and
+//    the orthonormal simplex (Proriol-Koornwinder-Dubiner) basis on the
+//    tetrahedron in collapsed coordinates, with its gradients, as set out in
+//    Hesthaven & Warburton, Nodal Discontinuous Galerkin Methods (Springer,
+//    2008), chapters 3, 6 and 10;
+//  * the warp & blend node set of Warburton, J. Eng. Math. 56 (2006);
+//  * Gauss-Jacobi rules from the eigenvalues of the Jacobi matrix
+//    (Golub & Welsch, Math. Comp. 23, 1969) and the conical product
+//    (Stroud) rule built from them.
 #include "refelem.hpp"
 
 #include <algorithm>

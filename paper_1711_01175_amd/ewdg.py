@@ -5,7 +5,17 @@ library.  PyTorch supplies device memory (the workspace and the device
 arrays passed in and out) and the HIP stream.  Importing works without a
 GPU; any call that needs the device fails loudly if the library or the GPU
 is missing.
+
+Stream ordering.  The library enqueues a context's work on the context's
+stream, which need not be torch's current stream.  Every method that passes
+device tensors makes the context's stream wait for torch's current stream
+first (the tensors' producers, and earlier users of recycled memory), makes
+torch's current stream wait for the context's stream afterwards (the
+tensors' consumers), and marks the tensors as used on the context's stream
+(record_stream), so the caching allocator does not hand their memory out
+again before that work has run.
 """
+import contextlib
 import ctypes
 import os
 
@@ -118,6 +128,7 @@ class Context:
         self.precision = int(precision)
         self._ws = None
         self._adj_ws = None
+        self._stream = int(stream or 0)
         h = _c_p()
         rc = self.lib.ewdg_create(self.N, self.precision, _c_p(stream), ctypes.byref(h))
         if rc != EWDG_OK:
@@ -162,6 +173,30 @@ class Context:
 
     def set_stream(self, stream):
         self._check(self.lib.ewdg_set_stream(self.h, _c_p(stream)), "set_stream")
+        self._stream = int(stream or 0)
+
+    def _stream_obj(self):
+        torch = _torch()
+        if self._stream == 0:
+            return torch.cuda.default_stream()
+        return torch.cuda.ExternalStream(self._stream)
+
+    @contextlib.contextmanager
+    def _ordered(self, *tensors):
+        """Order the context's stream against torch's current stream around
+        a library call that reads or writes the given device tensors."""
+        torch = _torch()
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream == self._stream:
+            yield
+            return
+        s = self._stream_obj()
+        s.wait_stream(cur)
+        yield
+        cur.wait_stream(s)
+        for t in tensors:
+            if t is not None and t.is_cuda:
+                t.record_stream(s)
 
     # ----------------------------------------------------------------- mesh
     def set_mesh(self, EToV, VXYZ):
@@ -208,8 +243,9 @@ class Context:
         nbytes = self.workspace_bytes(max_receivers, max_record_steps)
         if buffer is None:
             buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        self._check(self.lib.ewdg_bind_workspace(self.h, _ptr(buffer), buffer.numel() * buffer.element_size(),
-                                                 max_receivers, max_record_steps), "bind_workspace")
+        with self._ordered(buffer):
+            self._check(self.lib.ewdg_bind_workspace(self.h, _ptr(buffer), buffer.numel() * buffer.element_size(),
+                                                     max_receivers, max_record_steps), "bind_workspace")
         self._ws = buffer
         return buffer
 
@@ -230,14 +266,15 @@ class Context:
         else:
             qd = q.to(device="cuda", dtype=self.torch_dtype).contiguous()
             self._shape(qd, 9 * self.Np)
-            self._check(self.lib.ewdg_set_state(self.h, _ptr(qd), 1, float(t)), "set_state")
-            torch.cuda.current_stream().synchronize()
+            with self._ordered(qd):
+                self._check(self.lib.ewdg_set_state(self.h, _ptr(qd), 1, float(t)), "set_state")
 
     def get_state(self):
         torch = _torch()
         out = torch.empty((self.K, 9, self.Np), dtype=self.torch_dtype, device="cuda")
         t = _c_d()
-        self._check(self.lib.ewdg_get_state(self.h, _ptr(out), 1, ctypes.byref(t)), "get_state")
+        with self._ordered(out):
+            self._check(self.lib.ewdg_get_state(self.h, _ptr(out), 1, ctypes.byref(t)), "get_state")
         return out
 
     def project_quadrature(self, fq):
@@ -245,7 +282,8 @@ class Context:
         fq = fq.to(device="cuda", dtype=torch.float64).contiguous()
         self._shape(fq, 9 * self.Nq)
         out = torch.empty((self.K, 9, self.Np), dtype=self.torch_dtype, device="cuda")
-        self._check(self.lib.ewdg_project_quadrature(self.h, _ptr(fq), _ptr(out)), "project_quadrature")
+        with self._ordered(fq, out):
+            self._check(self.lib.ewdg_project_quadrature(self.h, _ptr(fq), _ptr(out)), "project_quadrature")
         return out
 
     def eval_quadrature(self, q=None):
@@ -255,7 +293,8 @@ class Context:
             assert q.is_cuda and q.dtype == self.torch_dtype and q.is_contiguous()
             self._shape(q, 9 * self.Np)
         qp = _c_p(None) if q is None else _ptr(q)
-        self._check(self.lib.ewdg_eval_quadrature(self.h, qp, _ptr(out)), "eval_quadrature")
+        with self._ordered(q, out):
+            self._check(self.lib.ewdg_eval_quadrature(self.h, qp, _ptr(out)), "eval_quadrature")
         return out
 
     # ------------------------------------------------- source and receivers
@@ -292,7 +331,8 @@ class Context:
         q = q.to(device="cuda", dtype=self.torch_dtype).contiguous()
         self._shape(q, 9 * self.Np)
         out = torch.empty_like(q)
-        self._check(self.lib.ewdg_rhs(self.h, float(t), _ptr(q), _ptr(out)), "rhs")
+        with self._ordered(q, out):
+            self._check(self.lib.ewdg_rhs(self.h, float(t), _ptr(q), _ptr(out)), "rhs")
         return out
 
     def step(self, dt, nsteps):
@@ -322,9 +362,11 @@ class Context:
         nbytes = self.adjoint_workspace_bytes(max_steps, checkpoint_every, overlapped)
         if buffer is None:
             buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        self._check(self.lib.ewdg_bind_adjoint_workspace(self.h, _ptr(buffer), buffer.numel() * buffer.element_size(),
-                                                         int(max_steps), int(checkpoint_every)),
-                    "bind_adjoint_workspace")
+        with self._ordered(buffer):
+            self._check(self.lib.ewdg_bind_adjoint_workspace(self.h, _ptr(buffer),
+                                                             buffer.numel() * buffer.element_size(),
+                                                             int(max_steps), int(checkpoint_every)),
+                        "bind_adjoint_workspace")
         self._adj_ws = buffer
         return buffer
 
@@ -338,8 +380,9 @@ class Context:
             self._shape(q, 9 * self.Np)
         out = torch.empty_like(y)
         g = torch.empty((self.K, 3), dtype=torch.float64, device="cuda") if grad else None
-        self._check(self.lib.ewdg_rhs_adjoint(self.h, float(t), _c_p(None) if q is None else _ptr(q), _ptr(y),
-                                              _ptr(out), _c_p(None) if g is None else _ptr(g)), "rhs_adjoint")
+        with self._ordered(y, q, out, g):
+            self._check(self.lib.ewdg_rhs_adjoint(self.h, float(t), _c_p(None) if q is None else _ptr(q), _ptr(y),
+                                                  _ptr(out), _c_p(None) if g is None else _ptr(g)), "rhs_adjoint")
         return (out, g) if grad else out
 
     def forward_misfit(self, dt, nsteps, data):
@@ -357,8 +400,9 @@ class Context:
         torch = _torch()
         g = torch.empty((self.K, 3), dtype=torch.float64, device="cuda")
         qb = torch.empty((self.K, 9, self.Np), dtype=self.torch_dtype, device="cuda") if want_qbar0 else None
-        self._check(self.lib.ewdg_adjoint_gradient(self.h, _ptr(g), _c_p(None) if qb is None else _ptr(qb)),
-                    "adjoint_gradient")
+        with self._ordered(g, qb):
+            self._check(self.lib.ewdg_adjoint_gradient(self.h, _ptr(g), _c_p(None) if qb is None else _ptr(qb)),
+                        "adjoint_gradient")
         return g, qb
 
 
@@ -372,15 +416,28 @@ def batch_table_bytes(n):
 
 def step_batch(contexts, dts, nsteps, table, stream=None):
     """ewdg_step_batch over Context objects; table is a torch device buffer
-    of at least batch_table_bytes(len(contexts)) bytes."""
+    of at least batch_table_bytes(len(contexts)) bytes.  The work runs on
+    `stream` (a hipStream_t; torch's current stream if None)."""
     n = len(contexts)
     if n == 0:
         return
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
     hs = (_c_p * n)(*[c.h for c in contexts])
     d = (_c_d * n)(*[float(x) for x in dts])
+    cur = torch.cuda.current_stream()
+    s = cur if int(stream) == cur.cuda_stream else (
+        torch.cuda.default_stream() if int(stream) == 0 else torch.cuda.ExternalStream(int(stream)))
+    if s is not cur:
+        s.wait_stream(cur)
     rc = load().ewdg_step_batch(hs, n, d, int(nsteps), _ptr(table), table.numel() * table.element_size(),
                                 _c_p(stream))
+    if s is not cur:
+        cur.wait_stream(s)
+        table.record_stream(s)
     if rc != EWDG_OK:
         msgs = "; ".join(c.lib.ewdg_last_error(c.h).decode() for c in contexts
                          if c.lib.ewdg_last_error(c.h))
         raise EwdgError(rc, "step_batch " + msgs)
+

@@ -157,17 +157,26 @@ class Server:
         live.dt = ctx.cfl_dt(self.cfl)
         self.setup_stream.synchronize()
         ctx.set_stream(self.stream.cuda_stream)
+        # the workspace was allocated on the setup stream and is used on the
+        # chunk and retire streams: its memory is recycled only after the
+        # work queued there when it is freed
+        live.ws.record_stream(self.stream)
+        live.ws.record_stream(self.retire_stream)
         live.t_admit = now
 
     def _finish(self, live, now, stats):
         req, ctx = live.req, live.ctx
         # the request's last chunk is complete; read back on a stream of its
-        # own so the read-back does not wait for the chunk queued after it
+        # own so the read-back does not wait for the chunk queued after it.
+        # The retire stream is torch's current stream here, so the device
+        # copy of the state and its transfer to the host are ordered on it.
         ctx.set_stream(self.retire_stream.cuda_stream)
-        traces = ctx.receivers() if len(req.receivers) else np.zeros((0, 0, 3))
-        state = ctx.get_state().cpu().numpy() if self.keep_state else None
+        with self.torch.cuda.stream(self.retire_stream):
+            traces = ctx.receivers() if len(req.receivers) else np.zeros((0, 0, 3))
+            state = ctx.get_state().cpu().numpy() if self.keep_state else None
+            energy = ctx.energy()
         stats.results.append(Result(req.rid, req.arrival, live.t_admit, now, now - req.arrival, ctx.K,
-                                    req.N, req.nsteps, ctx.energy(), traces, state))
+                                    req.N, req.nsteps, energy, traces, state))
         stats.dof_stages += ctx.K * ctx.Np * 9 * 5 * req.nsteps
         ctx.close()
         live.ws = None

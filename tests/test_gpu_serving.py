@@ -2,8 +2,9 @@
 
 Each request's result must be the same alone and in any mix: the batched
 launch runs exactly the per-request arithmetic of a solo ewdg_step, so the
-comparison is bitwise.  ewdg_step itself is pinned to the oracle by the
-parity tests.
+comparison is bitwise.  Served requests are also compared with the FP64
+oracle run of the same request (relative L2 at the quadrature points
+<= 1e-12 in FP64, <= 1e-5 in FP32).
 """
 import numpy as np
 import pytest
@@ -90,3 +91,48 @@ def test_server_continuous_batching_alone_vs_mix():
         assert np.array_equal(res.state, by[r.rid].state)
         assert np.array_equal(res.traces, by[r.rid].traces)
         assert res.traces.shape == (r.nsteps, len(rec), 3) and np.abs(res.traces).max() > 0
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_served_requests_match_oracle(precision):
+    """Three requests (N = 3, 4 and 5 on cubes of 3^3 and 4^3 hexahedra, each
+    with its own medium and source) served together with two slots, so one
+    joins while the others run; every result against the oracle."""
+    import paper_1711_01175_amd as P
+    from helpers import quad_points
+    from oracle import timestep
+    from oracle.dg import Elastic
+    from oracle.reference import stroud_rule
+    from paper_1711_01175_amd.serving import Server
+    reqs = request_stream(3, n_range=(3, 4), degrees=(3, 4, 5), nsteps=16, seed0=90)
+    for r, N in zip(reqs, (3, 4, 5)):
+        r.N = N
+    reqs[2].nsteps = 10
+    tol = 1e-12 if precision == 64 else 1e-5
+    budget = 0
+    for r in reqs:
+        c = P.Context(r.N, precision)
+        c.set_mesh(*r.mesh())
+        budget += c.workspace_bytes()
+        c.close()
+    srv = Server(budget_bytes=budget, slots=2, precision=precision, chunk_steps=4, keep_state=True)
+    stats = srv.run(reqs)
+    assert len(stats.results) == 3 and not stats.rejected
+    by = {x.rid: x for x in stats.results}
+    for r in reqs:
+        EToV, VXYZ = r.mesh()
+        xyz = quad_points(VXYZ, stroud_rule(r.N)[0])
+        mat = r.material(xyz)
+        op = Elastic(r.N, VXYZ, *mat)
+        src = timestep.Source(r.xs, r.direction, 1.0, r.f0, r.t0)
+        dt = timestep.cfl_dt(op, 0.5)
+        cT, _, _ = timestep.run(op, np.zeros((op.K, 9, op.Np)), dt, r.nsteps, source=src)
+        ref = op.to_q(cT)
+        c = P.Context(r.N, precision)
+        c.set_mesh(EToV, VXYZ)
+        c.bind_workspace()
+        c.set_material(*mat)
+        got = c.eval_quadrature(torch.from_numpy(by[r.rid].state).cuda()).cpu().numpy()
+        err = op.l2_q(got - ref) / op.l2_q(ref)
+        print("served", r.rid, "N", r.N, "K", op.K, "steps", r.nsteps, "rel_l2", f"{err:.3e}", flush=True)
+        assert err <= tol

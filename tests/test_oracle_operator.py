@@ -271,3 +271,35 @@ def test_point_values_reproduce_polynomials():
     pts = rng.uniform(-0.99, 0.99, size=(25, 3))
     got = op.eval_points(c, pts)
     assert np.abs(got - poly(pts)).max() <= 1e-12
+
+
+def test_point_values_on_the_singular_edge_of_the_collapsed_map():
+    """Values at mesh vertices, on edges and on faces, which in the owning
+    element's reference coordinates include the vertex t = 1 and the edge
+    s + t = 0 where the collapsed map is singular: the projection of a global
+    degree-N polynomial must still give the polynomial's value (the
+    singularity is removable for values), at N = 2, 3 and 4."""
+    from oracle.reference import Basis
+    rng = np.random.default_rng(13)
+    for N in (2, 3, 4):
+        # reference vertices and points on the singular edge (r = -1, s + t = 0)
+        B = Basis(N)
+        edge = np.array([[-1.0, -1.0, 1.0], [-1.0, 1.0, -1.0], [1.0, -1.0, -1.0], [-1.0, -1.0, -1.0],
+                         [-1.0, 0.4, -0.4], [-1.0, -0.2, 0.2], [-1.0, 0.0, 0.0]])
+        assert np.all(np.isfinite(B.eval(edge)))
+        # the values at the singular points are limits of nearby interior ones
+        inner = edge + 1e-8 * (np.array([-0.5, -0.5, -0.5]) - edge)      # towards the centroid
+        assert np.abs(B.eval(edge) - B.eval(inner)).max() <= 1e-5
+        op, EToV, VXYZ, xyz, _ = oracle_case(N, 4, shuffle_seed=30 + N)
+        cf = rng.standard_normal((9, 4))
+
+        def poly(p):
+            x, y, z = p[..., 0], p[..., 1], p[..., 2]
+            basis = np.stack([np.ones_like(x), x * y - z, x ** N + y, y * z ** (N - 1)], axis=-1)
+            return basis @ cf.T
+
+        c = op.project_q(np.moveaxis(poly(xyz), -1, 1))
+        pts = np.array([[0.0, 0.5, -0.5], [0.5, 0.5, 0.5], [0.25, 0.0, 0.1], [0.1, 0.1, 0.3],
+                        [0.5, -0.5, 0.2], [-0.5, -0.5, -0.5], [0.0, 0.0, 0.0]])
+        got = op.eval_points(c, pts)
+        assert np.abs(got - poly(pts)).max() <= 1e-11, N
