@@ -116,9 +116,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   constexpr bool SIGL = NfpK * SF + Np * SE <= TL::Y;
   T* Ssig = sY + NfpK * SF;
 
-  // ---- face-point gathers, one face ahead of use: the neighbour's velocity
-  // and stresses at the matching node (and the own stresses when they are
-  // not kept in LDS).
+  // ---- face-point gathers, two faces ahead of use (buffers pa, pb in
+  // turn): the neighbour's velocity and stresses at the matching node (and
+  // the own stresses when they are not kept in LDS).
+  // (one face ahead where the own stresses come from global memory too:
+  // there the second buffer would not fit in the registers)
+  constexpr bool G2 = SIGL;
+  FacePt<T> pa[FPT], pb[G2 ? FPT : 1];
   auto gather = [&](int f, FacePt<T>* pf) {
 #pragma unroll
     for (int p = 0; p < FPT; ++p) {
@@ -147,32 +151,71 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     }
   };
 
-  // ---- element data: geometry, velocities (B layout), zero paddings
-  for (int x = tid; x < E * 27; x += NT) {
-    const int e = x / 27, m = x % 27;
-    T v = T(0);
-    if (e0 + e < Ke) {
-      if (m < 9) v = a.geo[(e0 + e) * 9 + m];
-      else if (m < 25) v = a.fgeo[(e0 + e) * 16 + (m - 9)];
-      else v = a.Z[(e0 + e) * 2 + (m - 25)];
-    }
-    sgeo[e * 32 + m] = v;
-  }
+  // ---- element data: geometry, velocities (B layout) and, where they fit,
+  // the own stresses, all loads issued before any is used (one memory
+  // latency for the whole start-up); zero paddings
   T* Sv = sX;                // [NpK][SV]  v_c of element e at column c*16+e
   T* SG = sX + NpK * SV;     // [NpK][SV]  G^k_c for the current direction k
-  for (int x = tid; x < E * 3 * Np; x += NT) {
-    const int e = x / (3 * Np), rem = x % (3 * Np), c = rem / Np, j = rem % Np;
-    const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
-    const T v = a.qin[ge * 9 * Np + c * Np + j];
-    Sv[j * SV + c * 16 + (e ^ sw(j))] = (e0 + e < Ke) ? v : T(0);
+  {
+    constexpr int NGL = (E * 27 + NT - 1) / NT;
+    constexpr int NVL = (E * 3 * Np + NT - 1) / NT;
+    constexpr int NSL = SIGL ? (E * 6 * Np + NT - 1) / NT : 1;
+    T gv0[NGL], vv[NVL], sv[NSL];
+#pragma unroll
+    for (int p = 0; p < NGL; ++p) {
+      const int x = tid + p * NT;
+      const int e = x / 27, m = x % 27;
+      const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+      const T* src = m < 9 ? a.geo + ge * 9 + m : (m < 25 ? a.fgeo + ge * 16 + (m - 9) : a.Z + ge * 2 + (m - 25));
+      gv0[p] = x < E * 27 ? *src : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < NVL; ++p) {
+      const int x = tid + p * NT;
+      const int xc = x < E * 3 * Np ? x : E * 3 * Np - 1;
+      const int e = xc / (3 * Np), rem = xc % (3 * Np);
+      const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+      vv[p] = a.qin[ge * 9 * Np + rem];
+    }
+    if constexpr (SIGL) {
+#pragma unroll
+      for (int p = 0; p < NSL; ++p) {
+        const int x = tid + p * NT;
+        const int xc = x < E * 6 * Np ? x : E * 6 * Np - 1;
+        const int e = xc / (6 * Np), rem = xc % (6 * Np);
+        const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+        sv[p] = a.sin[ge * 6 * Np + rem];
+      }
+    }
+    // the first faces' gathers stay in flight during the volume terms
+    gather(0, pa);
+    if constexpr (G2) gather(1, pb);
+#pragma unroll
+    for (int p = 0; p < NGL; ++p) {
+      const int x = tid + p * NT;
+      const int e = x / 27, m = x % 27;
+      if (x < E * 27) sgeo[e * 32 + m] = e0 + e < Ke ? gv0[p] : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < NVL; ++p) {
+      const int x = tid + p * NT;
+      const int e = x / (3 * Np), rem = x % (3 * Np), c = rem / Np, j = rem % Np;
+      if (x < E * 3 * Np) Sv[j * SV + c * 16 + (e ^ sw(j))] = (e0 + e < Ke) ? vv[p] : T(0);
+    }
+    if constexpr (SIGL) {
+#pragma unroll
+      for (int p = 0; p < NSL; ++p) {
+        const int x = tid + p * NT;
+        const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, j = rem % Np;
+        if (x < E * 6 * Np) Ssig[j * SE + m * 16 + e] = (e0 + e < Ke) ? sv[p] : T(0);
+      }
+    }
   }
   for (int x = tid; x < (NpK - Np) * SV; x += NT) {
     Sv[Np * SV + x] = T(0);
     SG[Np * SV + x] = T(0);
   }
   constexpr int NPT = (E * Np + NT - 1) / NT;
-  FacePt<T> pf[FPT];
-  gather(0, pf);   // in flight during the volume terms
   __syncthreads();
 
   // ---- volume terms: div sigma = sum_k D_k G^k with the contravariant
@@ -197,13 +240,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         const int e = x / Np, j = x % Np;
         T sg[6];
         const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
-        if (!SIGL || k == 0) {
+        if constexpr (!SIGL) {
 #pragma unroll
           for (int m = 0; m < 6; ++m) sg[m] = a.sin[ge * 6 * Np + m * Np + j];
-          if constexpr (SIGL) {
-#pragma unroll
-            for (int m = 0; m < 6; ++m) Ssig[j * SE + m * 16 + e] = sg[m];
-          }
         } else {
 #pragma unroll
           for (int m = 0; m < 6; ++m) sg[m] = Ssig[j * SE + m * 16 + e];
@@ -249,8 +288,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // ---- interface corrections, one face at a time, lifted on the matrix cores
   T* Sf = sY;  // [NfpK][SF]
   for (int x = tid; x < (NfpK - Nfp) * SF; x += NT) Sf[Nfp * SF + x] = T(0);
-#pragma unroll 1
-  for (int f = 0; f < 4; ++f) {
+  // face f uses the gathers of buffer pf and refills it with face fn
+  auto face = [&](const int f, FacePt<T>* pf, const int fn) {
     T lf[KF];
     if (own) {
       const T* Lr = a.Lpad + ((f * RT + R) * KF) * 64 + l;
@@ -296,7 +335,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       fl[7 * 16] = fs * T(0.5) * (n[0] * dv[2] + n[2] * dv[0]);
       fl[8 * 16] = fs * T(0.5) * (n[0] * dv[1] + n[1] * dv[0]);
     }
-    if (f < 3) gather(f + 1, pf);   // next face's loads overlap this face's lift
+    if (fn < 4) gather(fn, pf);   // in flight during the lift(s) before its flux
     __syncthreads();
     if (own) {
 #pragma unroll
@@ -308,6 +347,17 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       }
     }
     __syncthreads();
+  };
+  if constexpr (G2) {
+    face(0, pa, 2);
+    face(1, pb, 3);
+    face(2, pa, 4);
+    face(3, pb, 4);
+  } else {
+    face(0, pa, 1);
+    face(1, pa, 2);
+    face(2, pa, 3);
+    face(3, pa, 4);
   }
 
   // ---- right-hand side to LDS: velocity rows [NpK][SV] for the mass
@@ -350,44 +400,47 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 
   // ---- per (element, node): density-weighted mass inverse on the velocity
   // rows, point source, LSRK update of all nine fields with coalesced
-  // accesses; the new strains go to LDS for the projection.
-#pragma unroll
-  for (int p = 0; p < NPU; ++p) {
+  // accesses; the new strains go to LDS for the projection.  Each thread
+  // takes NPU (element, node) pairs in turn; the loads of pair p + 1 (its W
+  // row, old residual and state) are issued before pair p is computed, from
+  // clamped (valid) addresses, so one memory latency covers the whole step.
+  constexpr int NQV = VL ? 6 : 9;        // state values read from global memory
+  auto upd_load = [&](int p, T* w, T* rv, T* qv) {
     const int x = tid + p * NT;
-    if (x >= E * Np) break;
+    const int xc = x < E * Np ? x : E * Np - 1;
+    const int e = xc / Np, i = xc % Np;
+    const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+    const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
+#pragma unroll
+    for (int j = 0; j < Np; ++j) w[j] = Wm[j * Np];
+    const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
+    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rv[c] = a.out[base + c * Np];
+#pragma unroll
+      for (int c = 0; c < NQV; ++c) qv[c] = a.qin[base + (c + 9 - NQV) * Np];
+    }
+  };
+  // o[0..2] += sum over j in [j0, j0 + n) of W_ij rhs_v[j]
+  auto wdot = [&](int p, const T* w, int j0, int n, T* o) {
+    const int x = tid + p * NT;
+    const int e = (x < E * Np ? x : E * Np - 1) / Np;
+#pragma unroll
+    for (int u = 0; u < n; ++u) {
+      const int j = j0 + u;
+      const int es = e ^ sw(j);
+      o[0] += w[u] * Srv[j * SV + es];
+      o[1] += w[u] * Srv[j * SV + 16 + es];
+      o[2] += w[u] * Srv[j * SV + 32 + es];
+    }
+  };
+  // source, LSRK update and stores of pair p, given o[0..2] = W rhs_v
+  auto upd_finish = [&](int p, T* o, const T* rv, const T* qv) {
+    const int x = tid + p * NT;
     const int e = x / Np, i = x % Np;
     const int ge = e0 + e;
-    if (ge >= Ke) continue;
-    const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
+    if (x >= E * Np || ge >= Ke) return;
     const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
-    T rv[9], qv[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      rv[c] = (MODE != 0) ? a.out[base + c * Np] : T(0);
-      qv[c] = (MODE != 0) ? ((VL && c < 3) ? vold[p][c < 3 ? c : 0] : a.qin[base + c * Np]) : T(0);
-    }
-    T o[9];
-    o[0] = 0;
-    o[1] = 0;
-    o[2] = 0;
-    // W column in chunks whose loads issue together (one round trip per chunk)
-    constexpr int CW = Np < EWDG_CW ? Np : EWDG_CW;
-#pragma unroll
-    for (int j0 = 0; j0 < Np; j0 += CW) {
-      T w[CW];
-#pragma unroll
-      for (int u = 0; u < CW; ++u) w[u] = (j0 + u < Np) ? Wm[(j0 + u) * Np] : T(0);
-#pragma unroll
-      for (int u = 0; u < CW; ++u) {
-        if (j0 + u < Np) {
-          const int j = j0 + u;
-          const int es = e ^ sw(j);
-          o[0] += w[u] * Srv[j * SV + es];
-          o[1] += w[u] * Srv[j * SV + 16 + es];
-          o[2] += w[u] * Srv[j * SV + 32 + es];
-        }
-      }
-    }
     if (ge == a.src_elem) {
       const T sv = a.srcval * a.svec[i];
       o[0] += sv * a.dir0;
@@ -405,16 +458,68 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       if (MODE == 0) {
         a.out[base + c * Np] = o[c];
       } else {
+        const T q0 = (VL && c < 3) ? vold[p][c < 3 ? c : 0] : qv[c - (9 - NQV) < 0 ? 0 : c - (9 - NQV)];
         const T rr = a.a * rv[c] + a.dt * o[c];
-        const T qn = qv[c] + a.b * rr;
+        const T qn = q0 + a.b * rr;
         a.out[base + c * Np] = rr;
         a.qout[base + c * Np] = qn;
         if (c >= 3) Se[i * SE + (c - 3) * 16 + e] = qn;
       }
     }
+  };
+#ifndef EWDG_UPD_PIPE
+#define EWDG_UPD_PIPE 0
+#endif
+  if constexpr (EWDG_UPD_PIPE && Np <= 35) {
+    T wA[Np], rA[9], qA[NQV], wB[Np], rB[9], qB[NQV];
+    upd_load(0, wA, rA, qA);
+#pragma unroll
+    for (int p = 0; p < NPU; ++p) {
+      if (p + 1 < NPU) {
+        if (p & 1) upd_load(p + 1, wA, rA, qA);
+        else upd_load(p + 1, wB, rB, qB);
+      }
+      T o[9] = {0, 0, 0};
+      if (p & 1) {
+        wdot(p, wB, 0, Np, o);
+        upd_finish(p, o, rB, qB);
+      } else {
+        wdot(p, wA, 0, Np, o);
+        upd_finish(p, o, rA, qA);
+      }
+    }
+  } else {
+    // one pair at a time, the W row in chunks of CW values whose loads issue
+    // together (the rows of the larger degrees do not fit in the registers)
+    constexpr int CW = Np < EWDG_CW ? Np : EWDG_CW;
+#pragma unroll
+    for (int p = 0; p < NPU; ++p) {
+      const int x = tid + p * NT;
+      const int xc = x < E * Np ? x : E * Np - 1;
+      const int e = xc / Np, i = xc % Np;
+      const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+      const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
+      T rv[9], qv[NQV];
+      if constexpr (MODE != 0) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) rv[c] = a.out[base + c * Np];
+#pragma unroll
+        for (int c = 0; c < NQV; ++c) qv[c] = a.qin[base + (c + 9 - NQV) * Np];
+      }
+      const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
+      T o[9] = {0, 0, 0};
+#pragma unroll
+      for (int j0 = 0; j0 < Np; j0 += CW) {
+        constexpr int n0 = CW;
+        T w[n0];
+#pragma unroll
+        for (int u = 0; u < n0; ++u) w[u] = (j0 + u < Np) ? Wm[(j0 + u) * Np] : T(0);
+        wdot(p, w, j0, (Np - j0) < CW ? (Np - j0) : CW, o);
+      }
+      upd_finish(p, o, rv, qv);
+    }
   }
   if (MODE == 0) return;
-  __syncthreads();
 
   // ---- sigma_h of the new state: strains at the quadrature points (matrix
   // cores), Hooke's law with the sampled lambda, mu, and the L2_Q projection
@@ -424,6 +529,40 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // loaded once per tile and feeds six independent products.
   T* Sq = sY;  // [QC][SQ]
   constexpr int QC = TL::QC, NQC = (QT * 16 + QC - 1) / QC, KQ = QC / 4;
+  // each chunk has QC/16 <= NW quadrature row tiles, so a wave takes at most
+  // one per chunk: row tile c QC/16 + w of chunk c, if w < QC/16
+  static_assert(QC / 16 <= NW, "one quadrature row tile per wave and chunk");
+  const bool qrow = w < QC / 16;
+  // lambda and 2 mu at this lane's four rows of quadrature row tile Rq
+  // (clamped loads; rows past Nq and elements past K are zeroed after)
+  auto lm_load = [&](int Rq, T* lam, T* mu2) {
+    const int ge = e0 + lr;
+    const int gc = ge < Ke ? ge : Ke - 1;
+    constexpr int NqP = TL::NqP;
+    const T* lmr = a.lm + static_cast<int64_t>(gc) * 2 * NqP;
+    if constexpr (sizeof(T) == 4) {
+      // rows 4 lg .. 4 lg + 3 of the tile are contiguous: one 16-byte load each
+      const int q4 = Rq * 16 + 4 * lg;
+      const int qs = q4 + 4 <= NqP ? q4 : NqP - 4;
+      const float4 l4 = *reinterpret_cast<const float4*>(lmr + qs);
+      const float4 m4 = *reinterpret_cast<const float4*>(lmr + NqP + qs);
+      lam[0] = l4.x; lam[1] = l4.y; lam[2] = l4.z; lam[3] = l4.w;
+      mu2[0] = m4.x; mu2[1] = m4.y; mu2[2] = m4.z; mu2[3] = m4.w;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = Rq * 16 + M::row(lg, r);
+        const int qq = q < Nq ? q : Nq - 1;
+        lam[r] = lmr[qq];
+        mu2[r] = lmr[NqP + qq];
+      }
+    }
+  };
+  // the first chunk's lambda, mu: issued before the barrier that ends the
+  // update, in flight while the other waves finish it
+  T lamN[4], muN[4];
+  if (qrow && w < QT) lm_load(w, lamN, muN);
+  __syncthreads();
   acc_t pq[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) pq[m] = acc_t{0, 0, 0, 0};
@@ -438,41 +577,22 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
       for (int u = 0; u < KQ; ++u) pf2[u] = (4 * u < rows) ? Pr[u * 64] : T(0);
     }
-#pragma unroll 1
-    for (int Rq = q0 / 16 + w; Rq < QT && Rq * 16 < q0 + QC; Rq += NW) {
+    const int Rq = q0 / 16 + w;
+    if (qrow && Rq < QT) {
       T vf[KD];
       const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
 #pragma unroll
       for (int kk = 0; kk < KD; ++kk) vf[kk] = Vr[kk * 64];
-      const int ge = e0 + lr;
-      // unconditional loads from clamped (valid) indices, masked after
-      const int gc = ge < Ke ? ge : Ke - 1;
       T lam[4], mu2[4];
-      constexpr int NqP = TL::NqP;
-      const T* lmr = a.lm + static_cast<int64_t>(gc) * 2 * NqP;
-      if constexpr (sizeof(T) == 4) {
-        // rows 4 lg .. 4 lg + 3 of the tile are contiguous: one 16-byte load each
-        const int q4 = Rq * 16 + 4 * lg;
-        const int qs = q4 + 4 <= NqP ? q4 : NqP - 4;
-        const float4 l4 = *reinterpret_cast<const float4*>(lmr + qs);
-        const float4 m4 = *reinterpret_cast<const float4*>(lmr + NqP + qs);
-        lam[0] = l4.x; lam[1] = l4.y; lam[2] = l4.z; lam[3] = l4.w;
-        mu2[0] = T(2) * m4.x; mu2[1] = T(2) * m4.y; mu2[2] = T(2) * m4.z; mu2[3] = T(2) * m4.w;
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int q = Rq * 16 + M::row(lg, r);
-          const int qq = q < Nq ? q : Nq - 1;
-          lam[r] = lmr[qq];
-          mu2[r] = T(2) * lmr[NqP + qq];
-        }
-      }
+      const bool ge_ok = e0 + lr < Ke;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const bool ok = Rq * 16 + M::row(lg, r) < Nq && ge < Ke;
-        lam[r] = ok ? lam[r] : T(0);
-        mu2[r] = ok ? mu2[r] : T(0);
+        const bool ok = Rq * 16 + M::row(lg, r) < Nq && ge_ok;
+        lam[r] = ok ? lamN[r] : T(0);
+        mu2[r] = ok ? T(2) * muN[r] : T(0);
       }
+      // the next chunk's lambda, mu, in flight during this chunk
+      if (Rq + QC / 16 < QT) lm_load(Rq + QC / 16, lamN, muN);
       acc_t ac[6];
 #pragma unroll
       for (int m = 0; m < 6; ++m) ac[m] = acc_t{0, 0, 0, 0};
@@ -522,9 +642,32 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     }
   }
   __syncthreads();
-  for (int x = tid; x < E * 6 * Np; x += NT) {
-    const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, i = rem % Np;
-    if (e0 + e < Ke) a.sout[static_cast<int64_t>(e0 + e) * 6 * Np + rem] = Ss[i * SE + m * 16 + e];
+#ifndef EWDG_STORE_BATCH
+#define EWDG_STORE_BATCH 0
+#endif
+  if constexpr (!EWDG_STORE_BATCH) {
+#pragma unroll 2
+    for (int x = tid; x < E * 6 * Np; x += NT) {
+      const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, i = rem % Np;
+      if (e0 + e < Ke) a.sout[static_cast<int64_t>(e0 + e) * 6 * Np + rem] = Ss[i * SE + m * 16 + e];
+    }
+  } else {
+    // all LDS reads first, then the stores
+    constexpr int NSO = (E * 6 * Np + NT - 1) / NT;
+    T so[NSO];
+#pragma unroll
+    for (int p = 0; p < NSO; ++p) {
+      const int x = tid + p * NT;
+      const int xc = x < E * 6 * Np ? x : E * 6 * Np - 1;
+      const int e = xc / (6 * Np), rem = xc % (6 * Np), m = rem / Np, i = rem % Np;
+      so[p] = Ss[i * SE + m * 16 + e];
+    }
+#pragma unroll
+    for (int p = 0; p < NSO; ++p) {
+      const int x = tid + p * NT;
+      const int e = x / (6 * Np), rem = x % (6 * Np);
+      if (x < E * 6 * Np && e0 + e < Ke) a.sout[static_cast<int64_t>(e0 + e) * 6 * Np + rem] = so[p];
+    }
   }
 }
 
