@@ -79,7 +79,10 @@ int ewdg_set_stream(ewdg_ctx* ctx, void* hip_stream);
  * vertex ids with periodic images identified; VXYZ[K][4][3] holds each
  * element's own (unwrapped) vertex coordinates.  Every face must be shared
  * with exactly one other element (EWDG_EMESH otherwise), every element must
- * have positive orientation.  Host arrays. */
+ * have positive orientation.  Host arrays.  The kernels use 32-bit element
+ * offsets: K < 2^23 and K 9 Np, K Np^2, K 32 Nfp < 2^31 are required
+ * (EWDG_EINVAL before any array is read otherwise), e.g. K < 6.8 M at
+ * N = 4 and K < 1.99 M at N = 7. */
 int ewdg_set_mesh(ewdg_ctx* ctx, int64_t K, const int64_t* EToV, const double* VXYZ);
 
 /* Sizes of one element: nodes, face nodes, quadrature points. */

@@ -254,6 +254,15 @@ const char* ewdg_last_error(const ewdg_ctx* c) { return c ? c->err.c_str() : "nu
 
 int ewdg_set_mesh(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* VXYZ) {
   if (!c || !EToV || !VXYZ) return EWDG_EINVAL;
+  // the kernels index element data with 32-bit offsets and pack a
+  // neighbour index with a node index into 32 bits (nbr * 256 + node)
+  {
+    const int64_t Np = c->re.Np, NqP = (c->re.Nq + 3) / 4 * 4;
+    const int64_t lim = int64_t(1) << 31;
+    if (K >= (int64_t(1) << 23) || K * 9 * Np >= lim || K * Np * Np >= lim || K * 2 * NqP >= lim ||
+        K * 32 * c->re.Nfp >= lim)
+      return c->fail(EWDG_EINVAL, "mesh too large for the kernels' 32-bit element offsets");
+  }
   MeshData m;
   std::string e;
   const int rc = build_mesh(K, EToV, VXYZ, m, e);

@@ -123,21 +123,39 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // there the second buffer would not fit in the registers)
   constexpr bool G2 = SIGL;
   FacePt<T> pa[FPT], pb[G2 ? FPT : 1];
+  // The neighbour element and node of every face point of this thread,
+  // looked up once per tile (connectivity, then the node table), packed as
+  // nb * 256 + nn, so a face's gather issues its data loads with no
+  // dependent address loads in between.
+  int gofs[FPT][4];
+#pragma unroll
+  for (int p = 0; p < FPT; ++p) {
+    const int x = tid + p * NT;
+    const int xc = x < Nfp * E ? x : Nfp * E - 1;
+    const int e = xc / Nfp, j = xc % Nfp;
+    const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+    const int4 wd = *reinterpret_cast<const int4*>(a.conn + ge * 4);
+    const int w4[4] = {wd.x, wd.y, wd.z, wd.w};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int code = w4[f] & 31;
+      const int nn = a.nbrnode[((f * 4 + code / 6) * 6 + code % 6) * Nfp + j];
+      gofs[p][f] = (w4[f] >> 5) * 256 + nn;
+    }
+  }
   auto gather = [&](int f, FacePt<T>* pf) {
 #pragma unroll
     for (int p = 0; p < FPT; ++p) {
       const int x = tid + p * NT;
       const int e = x / Nfp, j = x % Nfp;   // element-major: lanes share a neighbour's cache lines
       if (x < Nfp * E && e0 + e < Ke) {
-        const int32_t wd = a.conn[(e0 + e) * 4 + f];
-        const int code = wd & 31;
-        const int nb = wd >> 5;
-        const int nn = a.nbrnode[((f * 4 + code / 6) * 6 + code % 6) * Nfp + j];
-        const int il = a.fmask[f * Nfp + j];
-        const T* so = a.sin + (e0 + e) * 6 * Np + il;
+        const int nb = gofs[p][f] >> 8;
+        const int nn = gofs[p][f] & 255;
         const T* qn = a.qin + nb * 9 * Np + nn;
         const T* sn = a.sin + nb * 6 * Np + nn;
         if constexpr (!SIGL) {
+          const int il = a.fmask[f * Nfp + j];
+          const T* so = a.sin + (e0 + e) * 6 * Np + il;
 #pragma unroll
           for (int m = 0; m < 6; ++m) pf[p].sm[m] = so[m * Np];
         }
@@ -982,7 +1000,7 @@ static hipError_t stage_impl(const Dev& d, int mode, const void* qin, const void
   using TL = Tile<N>;
   // the stage kernel indexes its arrays with 32-bit element offsets
   if (d.K * 9 * TL::Np >= (int64_t(1) << 31) || d.K * TL::Np * TL::Np >= (int64_t(1) << 31) ||
-      d.K * 2 * TL::NqP >= (int64_t(1) << 31))
+      d.K * 2 * TL::NqP >= (int64_t(1) << 31) || d.K >= (int64_t(1) << 23))
     return hipErrorInvalidValue;
   if (mode == 2 && !rhsv) return hipErrorInvalidValue;
   const StageArgs<T> a = stage_args<T>(d, qin, sin, qout, sout, out, c, rhsv);

@@ -202,12 +202,15 @@ def _sampled_rhs(case, prec, t=0.23):
 
 
 def _sample_errors(op, elems, got, ref):
-    """(relative L2_Q error over the sampled elements, largest per-element
-    relative L2_Q error)."""
+    """(relative L2_Q error over the sampled elements, largest element error
+    relative to the RMS element norm).  The second localises a wrong
+    element; it is scaled by the RMS norm rather than each element's own,
+    which is tiny where a source-driven wave has not arrived yet."""
     w = op.ref.wq[None, None, :] * op.mesh.J[elems][:, None, None]
     glob = float(np.sqrt(np.sum(w * (got - ref) ** 2) / np.sum(w * ref ** 2)))
-    per = np.sqrt(np.sum(w * (got - ref) ** 2, axis=(1, 2)) / np.sum(w * ref ** 2, axis=(1, 2)))
-    return glob, float(per.max())
+    err_e = np.sqrt(np.sum(w * (got - ref) ** 2, axis=(1, 2)))
+    rms = np.sqrt(np.mean(np.sum(w * ref ** 2, axis=(1, 2))))
+    return glob, float(err_e.max() / rms)
 
 
 @pytest.mark.timeout(300)

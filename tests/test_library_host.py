@@ -166,6 +166,23 @@ def test_empty_and_oversized_meshes_are_rejected():
         assert rc == B.EWDG_EINVAL, (K, rc)
 
 
+@pytest.mark.parametrize("N,K", [(1, 1 << 23), (4, 6_900_000), (7, 2_000_000), (5, 4_300_000)])
+def test_meshes_beyond_32bit_offsets_are_rejected(N, K):
+    """Meshes whose element data would overflow the kernels' 32-bit offsets
+    (K 9 Np >= 2^31, or K >= 2^23 for the packed neighbour index) are refused
+    with EWDG_EINVAL before any array is read (the arrays passed hold one
+    element)."""
+    import ctypes
+    lib = B.load()
+    c = P.Context(N, 32)
+    one = np.zeros((1, 4), dtype=np.int64)
+    xyz = np.zeros((1, 4, 3))
+    rc = lib.ewdg_set_mesh(c.h, ctypes.c_int64(K), one.ctypes.data_as(ctypes.c_void_p),
+                           xyz.ctypes.data_as(ctypes.c_void_p))
+    assert rc == B.EWDG_EINVAL
+    assert b"32-bit" in lib.ewdg_last_error(c.h)
+
+
 def test_empty_batch_and_null_arguments():
     import ctypes
     lib = B.load()
