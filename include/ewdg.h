@@ -191,6 +191,23 @@ int ewdg_batch_table_bytes(int n, size_t* bytes);
 int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps, void* table_dev,
                     size_t table_bytes, void* hip_stream);
 
+/* Batched stepping that allocates nothing, for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, arithmetic and results (bitwise) as
+ * ewdg_step_batch with a one-step table, minus the caller's table buffer:
+ * the launch table lives in a fixed device array of
+ * ewdg_static_table_max_bytes bytes (256 KiB; one copy per GPU, held until
+ * the process ends), filled from a fixed host array, and all work (one
+ * table upload and the launches per step) is enqueued on hip_stream.  No
+ * device or pinned memory, stream or event is created.  A batch whose
+ * one-step table (ewdg_batch_table_bytes(n)) exceeds that size is rejected
+ * with EWDG_ENOMEM before any work is queued.  Every call on a GPU shares
+ * that GPU's table: calls that overlap on one GPU (from several host
+ * threads, or on different streams whose work runs concurrently) race and
+ * must be serialised by the caller.  Errors as ewdg_step_batch. */
+int ewdg_static_table_max_bytes(size_t* bytes);
+int ewdg_step_batch_static(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps, void* hip_stream);
+
 /* ---------------------------------------------------------------- adjoint
  * Discrete adjoint of the fully discrete solve for the receiver misfit
  *     J = 1/2 dt sum_{n=1..nsteps} sum_r |v_h(x_r, t_n) - d_r(t_n)|^2

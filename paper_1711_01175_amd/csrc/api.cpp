@@ -926,6 +926,129 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
 
 }  // extern "C"
 
+// ------------------------------------------- batched stepping, no allocation
+// Launch tables of ewdg_step_batch_static live in this file-scope device
+// array (one copy per GPU, held until the process ends) and are filled from a
+// file-scope host array; nothing is allocated.  Host code never uses the
+// array's name as an address: its device address is taken once per device
+// with hipGetSymbolAddress and kept in scratch_dev.
+namespace {
+
+constexpr size_t kStaticTableBytes = 256 * 1024;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kStaticTableBytes];
+alignas(256) char scratch_host[kStaticTableBytes];
+void* scratch_dev[kMaxDevices] = {};
+
+// Device address of this GPU's copy of the table array (looked up on first
+// use, with the device current); nullptr on failure.
+void* static_table(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    scratch_dev[dev] = p;
+  }
+  return scratch_dev[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int ewdg_static_table_max_bytes(size_t* bytes) {
+  if (!bytes) return EWDG_EINVAL;
+  *bytes = kStaticTableBytes;
+  return EWDG_OK;
+}
+
+int ewdg_step_batch_static(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps, void* hip_stream) {
+  if (n < 0 || nsteps < 0 || (n > 0 && (!ctxs || !dts))) return EWDG_EINVAL;
+  if (n == 0 || nsteps == 0) return EWDG_OK;
+  if (!ctxs[0]) return EWDG_EINVAL;
+  size_t need_b = 0;
+  ewdg_batch_table_bytes(n, &need_b);
+  if (need_b > kStaticTableBytes)
+    return ctxs[0]->fail(EWDG_ENOMEM, "batch too large for the static launch table (ewdg_static_table_max_bytes)");
+  for (int i = 0; i < n; ++i) {
+    ewdg_ctx* c = ctxs[i];
+    if (!c) return EWDG_EINVAL;
+    if (int rc = need(c, true, true, true)) return c->fail(rc, "step_batch_static needs material");
+    if (!(dts[i] > 0.0)) return c->fail(EWDG_EINVAL, "non-positive dt");
+    if (c->nr > 0 && c->rec_count + nsteps > c->max_steps)
+      return c->fail(EWDG_ENOMEM, "receiver record capacity exceeded");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return c->fail(EWDG_EINVAL, "context repeated in a batch");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ctxs[0]->fail(EWDG_EHIP, "hipGetDevice failed");
+  char* table = static_cast<char*>(static_table(dev));
+  if (!table) return ctxs[0]->fail(EWDG_EHIP, "could not find the static launch table on this device");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t rec = batch_record_bytes();
+  const int E = stage_tile_elems();
+  // (degree, precision) groups in ascending order, as in ewdg_step_batch;
+  // fixed-size bookkeeping only (no host or device allocation)
+  static const int kDegrees[6] = {1, 2, 3, 4, 5, 7};
+  struct Launch { int N, prec, nreq, ntiles; size_t args_off, tiles_off; };
+  Launch launches[5 * 12];
+  for (int step = 0; step < nsteps; ++step) {
+    // the five stages' records and tile prefixes of this step, laid out as
+    // in ewdg_step_batch, in the host array
+    int nl = 0;
+    size_t off = 0;
+    for (int i = 0; i < 5; ++i) {
+      size_t rec_off = off, tiles_off = off + static_cast<size_t>(n) * rec;
+      for (int gN : kDegrees) {
+        for (int gp : {32, 64}) {
+          int32_t* ts = reinterpret_cast<int32_t*>(scratch_host + tiles_off);
+          int tiles = 0, m = 0;
+          for (int k = 0; k < n; ++k) {
+            ewdg_ctx* c = ctxs[k];
+            if (c->N != gN || c->prec != gp) continue;
+            const double dt = dts[k];
+            const int cs = (c->cur + i) & 1;
+            const StageCoef sc = coef(c, kRkA[i], kRkB[i], dt, c->t + kRkC[i] * dt);
+            stage_args_fill(c->d, c->d.q[cs], c->d.s[cs], c->d.q[1 - cs], c->d.s[1 - cs], c->d.res, sc,
+                            scratch_host + rec_off + static_cast<size_t>(m) * rec);
+            ts[m++] = tiles;
+            tiles += static_cast<int>((c->mesh.K + E - 1) / E);
+          }
+          if (m == 0) continue;
+          ts[m] = tiles;
+          launches[nl++] = Launch{gN, gp, m, tiles, rec_off, tiles_off};
+          rec_off += static_cast<size_t>(m) * rec;
+          tiles_off += static_cast<size_t>(m + 1) * 4;
+        }
+      }
+      off = (tiles_off + 255) / 256 * 256;
+    }
+    // pageable source: the copy has read the host array when it returns;
+    // stream order puts it after the previous step's launches
+    hipError_t e = hipMemcpyAsync(table, scratch_host, off, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return ctxs[0]->hip(e, "static batch table copy");
+    for (int k = 0; k < nl; ++k) {
+      const Launch& L = launches[k];
+      e = launch_stage_batch(L.N, L.prec, table + L.args_off, static_cast<int>(rec),
+                             reinterpret_cast<const int*>(table + L.tiles_off), L.nreq, L.ntiles, st);
+      if (e != hipSuccess) return ctxs[0]->hip(e, "batched stage");
+    }
+    for (int i = 0; i < n; ++i) {
+      ewdg_ctx* c = ctxs[i];
+      c->cur = (c->cur + 5) & 1;
+      c->t = c->t + dts[i];
+      if (c->nr > 0) {
+        e = launch_receivers(c->d, c->d.q[c->cur], c->nr, c->rec_count, st);
+        if (e != hipSuccess) return c->hip(e, "receivers");
+        ++c->rec_count;
+      }
+    }
+  }
+  return EWDG_OK;
+}
+
+}  // extern "C"
+
 // ------------------------------------------------------------------ adjoint
 namespace {
 

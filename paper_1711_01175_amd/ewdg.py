@@ -65,6 +65,8 @@ SIGNATURES = {
     "ewdg_energy": [_c_p, _P_d],
     "ewdg_batch_table_bytes": [_c_i, ctypes.POINTER(_c_sz)],
     "ewdg_step_batch": [ctypes.POINTER(_c_p), _c_i, ctypes.POINTER(_c_d), _c_i, _c_p, _c_sz, _c_p],
+    "ewdg_static_table_max_bytes": [ctypes.POINTER(_c_sz)],
+    "ewdg_step_batch_static": [ctypes.POINTER(_c_p), _c_i, ctypes.POINTER(_c_d), _c_i, _c_p],
     "ewdg_adjoint_workspace_bytes": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
     "ewdg_adjoint_workspace_bytes_overlapped": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
     "ewdg_bind_adjoint_workspace": [_c_p, _c_p, _c_sz, _c_i, _c_i],
@@ -441,3 +443,35 @@ def step_batch(contexts, dts, nsteps, table, stream=None):
                          if c.lib.ewdg_last_error(c.h))
         raise EwdgError(rc, "step_batch " + msgs)
 
+
+def static_table_max_bytes():
+    b = _c_sz()
+    rc = load().ewdg_static_table_max_bytes(ctypes.byref(b))
+    if rc != EWDG_OK:
+        raise EwdgError(rc, "static_table_max_bytes")
+    return b.value
+
+
+def step_batch_static(contexts, dts, nsteps, stream=None):
+    """ewdg_step_batch_static: as step_batch, with the launch table in the
+    library's fixed device array (no table buffer, nothing allocated)."""
+    n = len(contexts)
+    if n == 0:
+        return
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    hs = (_c_p * n)(*[c.h for c in contexts])
+    d = (_c_d * n)(*[float(x) for x in dts])
+    cur = torch.cuda.current_stream()
+    s = cur if int(stream) == cur.cuda_stream else (
+        torch.cuda.default_stream() if int(stream) == 0 else torch.cuda.ExternalStream(int(stream)))
+    if s is not cur:
+        s.wait_stream(cur)
+    rc = load().ewdg_step_batch_static(hs, n, d, int(nsteps), _c_p(stream))
+    if s is not cur:
+        cur.wait_stream(s)
+    if rc != EWDG_OK:
+        msgs = "; ".join(c.lib.ewdg_last_error(c.h).decode() for c in contexts
+                         if c.lib.ewdg_last_error(c.h))
+        raise EwdgError(rc, "step_batch_static " + msgs)
