@@ -101,6 +101,94 @@ def sweep_degrees(steps=10, warmup=2):
     print(json.dumps(out), flush=True)
 
 
+def _jacobians(VXYZ):
+    X = VXYZ
+    return np.abs(np.linalg.det(np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], -1))) / 8.0
+
+
+def _l2q(fq, J, wq):
+    """L2_Q norm of device values [K][9][Nq] with element Jacobians J [K]."""
+    import torch
+    w = torch.as_tensor(J, device=fq.device)[:, None, None] * torch.as_tensor(wq, device=fq.device)[None, None, :]
+    return float(torch.sqrt(torch.sum(w * fq * fq)))
+
+
+def _context(prec, N, EToV, VXYZ, perturb=False, max_rec=0, max_steps=0):
+    import torch
+
+    import paper_1711_01175_amd as P
+    from workloads import media
+    c = P.Context(N, prec, stream=torch.cuda.current_stream().cuda_stream)
+    c.set_mesh(EToV, VXYZ)
+    c.bind_workspace(max_rec, max_steps)
+    mat = media.smooth(c.quadrature_points())
+    if perturb:
+        mat = media.perturb_per_element(*mat, 3, frac=0.1)
+    c.set_material(*mat)
+    c.set_source([0.05, -0.10, 0.15], [0.0, 0.0, 1.0], 1.0, 5.0, 0.2)
+    return c
+
+
+def run_pair(N, n, nsteps, perturb=False, warmup=0):
+    """FP64 and FP32 runs of the same workload from a zero state: stage time
+    of each (HIP events around nsteps steps after `warmup` steps, on the
+    context's stream), energy, and the FP32 state's relative L2_Q distance
+    from the FP64 one after warmup + nsteps steps."""
+    import torch
+    EToV, VXYZ, _ = build_workload(n, N)
+    J = _jacobians(VXYZ)
+    out, fq = {}, {}
+    for prec in (64, 32):
+        c = _context(prec, N, EToV, VXYZ, perturb)
+        dt = c.cfl_dt(0.5)
+        c.step(dt, warmup)
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        c.step(dt, nsteps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        out[prec] = dict(stage_us=ev0.elapsed_time(ev1) * 1e3 / (5 * nsteps), energy=c.energy())
+        fq[prec] = c.eval_quadrature()
+        wq = c.reference_operator(8)
+        K, Np, Nq = c.K, c.Np, c.Nq
+        c.close()
+    rel = _l2q(fq[32] - fq[64], J, wq) / _l2q(fq[64], J, wq)
+    del fq
+    torch.cuda.empty_cache()
+    return dict(K=K, Np=Np, Nq=Nq, steps=warmup + nsteps, fp32=out[32], fp64=out[64], rel_l2_fp32_vs_fp64=rel)
+
+
+def run_golden():
+    """Both precisions on the 8^3 x 6 = 3,072-tet cube for the 1000 steps of
+    the stored oracle run (tests/golden/long_run_n8_N4.npz, written by the
+    committed script beside it): relative L2_Q error on the stored elements,
+    relative energy error and trace error, against the oracle's values."""
+    import torch
+    g = np.load(os.path.join(ROOT, "tests", "golden", "long_run_n8_N4.npz"))
+    N, nsteps = 4, int(g["nsteps"])
+    EToV, VXYZ, _ = build_workload(8, N)
+    J = _jacobians(VXYZ)[g["elems"]]
+    rec = g["receivers"]
+    res = {}
+    for prec in (64, 32):
+        c = _context(prec, N, EToV, VXYZ, max_rec=len(rec), max_steps=nsteps)
+        c.set_receivers(rec)
+        c.step(c.cfl_dt(0.5), nsteps)
+        got = c.eval_quadrature()[torch.as_tensor(g["elems"], device="cuda")]
+        ref = torch.as_tensor(g["fq"], device="cuda")
+        wq = c.reference_operator(8)
+        tr = c.receivers()
+        res[f"fp{prec}"] = {"rel_l2": _l2q(got - ref, J, wq) / _l2q(ref, J, wq),
+                            "energy_rel": abs(c.energy() - float(g["energy"])) / float(g["energy"]),
+                            "trace_err": float(np.abs(tr - g["traces"]).max() / np.abs(g["traces"]).max())}
+        c.close()
+    res["workload"] = (f"8^3 hexes x 6 = 3072 tets, N=4, same media and source as the headline, {nsteps} steps, "
+                       f"against the FP64 oracle's stored run on {len(g['elems'])} elements")
+    return res
+
+
 def build_workload(n, N):
     from workloads import media
     from workloads.mesh import kuhn_periodic_mesh
@@ -200,6 +288,7 @@ def run_serving(full=False):
     else:
         kw = dict(count=64, n_range=(6, 14), nsteps=100)
     budget, slots = 16 << 30, 32
+    calib_count = min(64, kw["count"])
 
     def progress(tag):
         last = [0.0]
@@ -211,8 +300,9 @@ def run_serving(full=False):
                       flush=True)
         return cb
 
+    # saturation: the stream's first calib_count requests, all queued at t = 0
     srv = Server(budget, slots=slots, precision=32)
-    calib = srv.run(request_stream(**kw), progress=progress("calibration"))
+    calib = srv.run(request_stream(**kw)[:calib_count], progress=progress("calibration"))
     srv.close()
     sat = len(calib.results) / calib.makespan
     rate = 0.8 * sat
@@ -224,7 +314,10 @@ def run_serving(full=False):
                             f"N~U{{3,4,5}}, {kw['nsteps']} LSRK steps each, FP32, random media and source per request, "
                             f"Poisson arrivals",
                 "full_stream": bool(full), "slots": slots, "budget_bytes": budget,
-                "saturation_req_per_s": sat, "arrival_rate_req_per_s": rate,
+                "saturation_req_per_s": sat, "saturation_from": f"the first {calib_count} requests queued at t=0",
+                "arrival_rate_req_per_s": rate,
+                "accuracy": "each served result equals a solo run bitwise (tests/test_gpu_serving.py); "
+                            "solo runs are held to the FP64 oracle at 1e-5 (FP32)",
                 "max_active": stats.max_active, "max_used_bytes": stats.max_used_bytes})
     return out
 
@@ -332,8 +425,10 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
-    ap.add_argument("--serving-full", action="store_true",
-                    help="serve the full 256-request stream (several minutes)")
+    ap.add_argument("--serving-reduced", action="store_true",
+                    help="serve a reduced 64-request stream instead of the full 256-request one")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the 1000-step FP32/FP64 and oracle comparisons and the N=7 leg")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the FP32 adjoint leg and print its JSON (for profiling)")
     ap.add_argument("--probe-copy", action="store_true",
@@ -388,6 +483,8 @@ def main():
                    "K": K, "N": args.N, "Np": Np, "dt": r32["dt"], "dof_per_stage": dof},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(32),
+                     "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, copy-calibrated, recorded in "
+                                     "profiles/k_stage_cube32_N4.md for these kernel sources (null if they differ)",
                      "kernel": "k_stage (fused stage)", "stage_us": round(stage_s * 1e6, 2),
                      "algorithmic_bytes_per_stage": algo},
     }
@@ -399,8 +496,34 @@ def main():
                         "roofline_frac": round(a64 / HBM_PEAK_GBS, 4), "achieved_GBs": round(a64, 1)}
         line["fp32_vs_fp64_speedup"] = round(r64["ms"] / r32["ms"], 3)
         line["energy_fp32_fp64"] = [r32["energy"], r64["energy"]]
+    if not args.no_accuracy:
+        # the headline workload after 1000 steps: FP32 against FP64 (the FP64
+        # stepping path is held to the oracle by the test suite)
+        acc = run_pair(args.N, args.n, 1000)
+        line["accuracy"] = {"rel_l2_fp32_vs_fp64_1000_steps": acc["rel_l2_fp32_vs_fp64"],
+                            "energy_fp32_fp64_1000_steps": [acc["fp32"]["energy"], acc["fp64"]["energy"]],
+                            "vs_oracle_3072_tets_1000_steps": run_golden()}
+        # high order (16^3 x 6 = 24,576 tets, N=7, +-10 % per-element media):
+        # stage time against the FP32 / FP64 matrix peaks, 500 steps, FP32 vs FP64
+        ho = run_pair(7, 16, 495, perturb=True, warmup=5)
+        Nfp7 = 36
+        fl = flops_per_element(ho["Np"], Nfp7, ho["Nq"]) * ho["K"]
+        line["high_order"] = {
+            "workload": f"16^3 hexes x 6 = {ho['K']} tets, N=7 (120 nodes), smooth media x (1 + 0.1 u) per element, "
+                        f"Ricker source, {ho['steps']} steps",
+            "bound": "mfma",
+            "fp32": {"stage_us": round(ho["fp32"]["stage_us"], 1),
+                     "GDOF_per_s": round(ho["K"] * ho["Np"] * 9 / ho["fp32"]["stage_us"] / 1e3, 2),
+                     "achieved_TFLOPs": round(fl / ho["fp32"]["stage_us"] / 1e6, 2), "peak_TFLOPs": PEAK_TFLOPS[32],
+                     "frac": round(fl / ho["fp32"]["stage_us"] / 1e6 / PEAK_TFLOPS[32], 4)},
+            "fp64": {"stage_us": round(ho["fp64"]["stage_us"], 1),
+                     "GDOF_per_s": round(ho["K"] * ho["Np"] * 9 / ho["fp64"]["stage_us"] / 1e3, 2),
+                     "achieved_TFLOPs": round(fl / ho["fp64"]["stage_us"] / 1e6, 2), "peak_TFLOPs": PEAK_TFLOPS[64],
+                     "frac": round(fl / ho["fp64"]["stage_us"] / 1e6 / PEAK_TFLOPS[64], 4)},
+            "rel_l2_fp32_vs_fp64": ho["rel_l2_fp32_vs_fp64"],
+            "flops_per_stage": fl}
     if not args.no_serving:
-        line["serving"] = run_serving(args.serving_full)
+        line["serving"] = run_serving(not args.serving_reduced)
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint()
     if args.cpu_seconds > 0:

@@ -167,6 +167,11 @@ int ewdg_time(const ewdg_ctx* ctx, double* t);
  * the quantity the upwind flux makes non-increasing in time.  Accumulated
  * in FP64 with a deterministic reduction; synchronises. */
 int ewdg_energy(ewdg_ctx* ctx, double* E);
+/* The same energy written to E_dev (one FP64 value of caller-owned device
+ * memory) by work enqueued on the context's stream, without synchronising:
+ * for health checks that ride on a running stream (the serving loop's
+ * per-request NaN and energy-growth guard). */
+int ewdg_energy_device(ewdg_ctx* ctx, double* E_dev);
 
 /* Batched stepping of many independent contexts (continuous-batching
  * serving).  Contexts are grouped by (degree, precision); every LSRK stage

@@ -2,6 +2,12 @@
 
 Compiles every source under csrc/ with hipcc and links one shared library
 next to this file.  Packed FP32 instructions are disabled for device code.
+
+build_sanitized() compiles the same sources with AddressSanitizer and
+UndefinedBehaviorSanitizer on the host code only (-Xarch_host before every
+sanitizer flag; GPU code is built as usual) and links them with the host
+check driver tests/host_check.cpp into _build/san/host_check, a program that
+exercises the library's host paths without a GPU.
 """
 import os
 import subprocess
@@ -47,6 +53,37 @@ def build(verbose=False):
     return OUT
 
 
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def _compile_san(args):
+    src, out = args
+    cmd = [HIPCC, "-x", "hip", "-c", src, "-o", out, "-O1", "-g", "-fPIC", "-std=c++17",
+           "-I" + CSRC, "-I" + os.path.join(ROOT, "include")] + DEVICE + SAN
+    subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL)
+    return out
+
+
+def build_sanitized(verbose=False):
+    """Host-sanitized build of the library sources and the host check
+    driver; returns the path of the executable."""
+    san = os.path.join(BUILD, "san")
+    os.makedirs(san, exist_ok=True)
+    jobs = [(os.path.join(CSRC, f), os.path.join(san, f + ".o")) for f in sources()]
+    jobs.append((os.path.join(ROOT, "tests", "host_check.cpp"), os.path.join(san, "host_check.o")))
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        objs = list(ex.map(_compile_san, jobs))
+    exe = os.path.join(san, "host_check")
+    subprocess.run([HIPCC, "-o", exe] + objs + ["--offload-arch=" + ARCH] + SAN, check=True)
+    if verbose:
+        print("built", exe)
+    return exe
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "sanitized":
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

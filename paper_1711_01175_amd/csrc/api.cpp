@@ -690,6 +690,12 @@ int ewdg_time(const ewdg_ctx* c, double* t) {
   return EWDG_OK;
 }
 
+int ewdg_energy_device(ewdg_ctx* c, double* E_dev) {
+  if (int rc = need(c, true, true, true)) return rc;
+  if (!E_dev) return EWDG_EINVAL;
+  return c->hip(launch_energy(c->d, c->d.q[c->cur], E_dev, c->stream), "energy");
+}
+
 int ewdg_energy(ewdg_ctx* c, double* E) {
   if (int rc = need(c, true, true, true)) return rc;
   if (!E) return EWDG_EINVAL;

@@ -63,6 +63,7 @@ SIGNATURES = {
     "ewdg_step": [_c_p, _c_d, _c_i],
     "ewdg_time": [_c_p, _P_d],
     "ewdg_energy": [_c_p, _P_d],
+    "ewdg_energy_device": [_c_p, _c_p],
     "ewdg_batch_table_bytes": [_c_i, ctypes.POINTER(_c_sz)],
     "ewdg_step_batch": [ctypes.POINTER(_c_p), _c_i, ctypes.POINTER(_c_d), _c_i, _c_p, _c_sz, _c_p],
     "ewdg_static_table_max_bytes": [ctypes.POINTER(_c_sz)],
@@ -349,6 +350,13 @@ class Context:
         e = _c_d()
         self._check(self.lib.ewdg_energy(self.h, ctypes.byref(e)), "energy")
         return e.value
+
+    def energy_device(self, out):
+        """Enqueue the energy into out (a one-element FP64 device tensor,
+        possibly a view into a larger one) on the context's stream; no sync."""
+        assert out.is_cuda and out.dtype == _torch().float64 and out.numel() >= 1
+        with self._ordered(out):
+            self._check(self.lib.ewdg_energy_device(self.h, _ptr(out)), "energy_device")
 
     # -------------------------------------------------------------- adjoint
     def adjoint_workspace_bytes(self, max_steps, checkpoint_every=50, overlapped=False):

@@ -14,8 +14,16 @@ Host preparation of arrived requests (worker threads) and device setup of
 admitted ones (a side stream) overlap the running chunk, and chunks are
 queued two deep so the device does not wait for the host between them.
 
+Each request's health is checked after every chunk: its energy (the FP64
+reduction of the library, enqueued on the chunk stream without a sync) must
+stay finite and must not grow by more than a set factor within one chunk.
+A request that fails stops advancing; its slot and memory are released once
+the chunks already queued with it have run, and the other requests are not
+affected (their arithmetic never reads another request's data).
+
 Only orchestration lives here; every step of the method runs in libewdg.
 """
+import math
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -59,6 +67,9 @@ class _Live:
     t_admit: float = 0.0
     ws: object = None
     material: object = None
+    inflight: int = 0    # queued chunks not yet completed
+    energy: float = 0.0  # energy after the last checked chunk
+    failed: str = None   # why the guard stopped the request
 
 
 @dataclass
@@ -77,9 +88,36 @@ class Result:
 
 
 @dataclass
+class Failure:
+    rid: int
+    arrival: float
+    admitted: float
+    stopped: float
+    reason: str
+    K: int
+    N: int
+    steps_done: int
+    energy: float
+
+
+def energy_check(previous, current, growth_limit):
+    """Health of a request after a chunk: None if fine, else the reason.
+
+    The energy must be finite; once it is positive it may not grow by more
+    than growth_limit within one chunk (the upwind flux only removes energy;
+    the point source adds it smoothly, far below such factors)."""
+    if not math.isfinite(current):
+        return "non-finite energy"
+    if growth_limit is not None and previous > 0.0 and current > growth_limit * previous:
+        return f"energy grew {current / previous:.3g}x within one chunk"
+    return None
+
+
+@dataclass
 class ServeStats:
     results: list = field(default_factory=list)
     rejected: list = field(default_factory=list)
+    failed: list = field(default_factory=list)
     makespan: float = 0.0
     dof_stages: float = 0.0
     max_used_bytes: int = 0
@@ -93,6 +131,7 @@ class ServeStats:
         return {
             "requests": len(self.results),
             "rejected": len(self.rejected),
+            "failed": len(self.failed),
             "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "makespan_s": self.makespan,
@@ -112,7 +151,7 @@ class Server:
     """
 
     def __init__(self, budget_bytes, slots=32, precision=32, chunk_steps=10, cfl=0.5,
-                 keep_state=False, prep_workers=4):
+                 keep_state=False, prep_workers=4, guard=True, growth_limit=1e6):
         import torch
         from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
@@ -130,6 +169,12 @@ class Server:
         # degree class runs on a stream of its own
         per_step = (B.batch_table_bytes(self.slots) + 255) // 256 * 256
         self.table = torch.empty(per_step * self.chunk, dtype=torch.uint8, device="cuda")
+        # per-request energies of the (at most two) chunks in flight
+        self.guard = bool(guard)
+        self.growth_limit = growth_limit
+        self.guard_dev = torch.zeros((2, self.slots), dtype=torch.float64, device="cuda")
+        self.guard_host = torch.zeros((2, self.slots), dtype=torch.float64).pin_memory()
+        self._gbuf = 0
 
     def close(self):
         self.pool.shutdown(wait=True)
@@ -181,7 +226,15 @@ class Server:
         ctx.close()
         live.ws = None
 
-    def run(self, requests, clock=time.perf_counter, sleep=time.sleep, progress=None):
+    def _release_failed(self, live, now, stats):
+        """Free a request the guard stopped (its queued chunks have run)."""
+        req, ctx = live.req, live.ctx
+        stats.failed.append(Failure(req.rid, req.arrival, live.t_admit, now, live.failed, ctx.K, req.N,
+                                    live.done, live.energy))
+        ctx.close()
+        live.ws = None
+
+    def run(self, requests, clock=time.perf_counter, sleep=time.sleep, progress=None, on_admit=None):
         """Serve requests arriving at req.arrival seconds after the start.
 
         Chunks are pipelined two deep: the next chunk of every running
@@ -190,13 +243,14 @@ class Server:
         work and the device does not idle between chunks.
 
         progress: optional callable(done, total, elapsed_s) called whenever
-        requests complete."""
+        requests complete.  on_admit: optional callable(rid, context) called
+        once a request's device setup is done, before its first chunk."""
         torch = self.torch
         stats = ServeStats()
         total = len(requests)
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         waiting, active = deque(), []      # waiting: futures of prepared requests, FIFO
-        inflight = deque()                 # (event, requests, steps) per queued chunk
+        inflight = deque()                 # (event, requests, steps, guard buffer) per queued chunk
         used = 0
         t0 = clock()
         while pending or waiting or active or inflight:
@@ -209,11 +263,21 @@ class Server:
                 chunk = min(self.chunk, min(a.req.nsteps - a.sched for a in launch))
                 B.step_batch([a.ctx for a in launch], [a.dt for a in launch], chunk, self.table,
                              self.stream.cuda_stream)
+                gb = None
+                if self.guard:
+                    gb = self._gbuf
+                    self._gbuf ^= 1
+                    with torch.cuda.stream(self.stream):
+                        for i, a in enumerate(launch):
+                            a.ctx.energy_device(self.guard_dev[gb, i:i + 1])
+                        self.guard_host[gb, :len(launch)].copy_(self.guard_dev[gb, :len(launch)],
+                                                                 non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(self.stream)
                 for a in launch:
                     a.sched += chunk
-                inflight.append((ev, launch, chunk))
+                    a.inflight += 1
+                inflight.append((ev, launch, chunk, gb))
             # admission in arrival order among prepared requests (the head of
             # the queue blocks the ones behind it until it is prepared)
             ready = []
@@ -230,6 +294,8 @@ class Server:
                     w.ctx.close()
                 elif id(w) in adm:
                     self._start(w, clock() - t0)
+                    if on_admit is not None:
+                        on_admit(w.req.rid, w.ctx)
                     used += w.footprint
                     admitted.append(w)
                 else:
@@ -248,19 +314,32 @@ class Server:
             # nothing more can be queued), then retire what it completed
             more = any(a.sched < a.req.nsteps for a in active)
             if inflight and (len(inflight) >= 2 or not more):
-                ev, lives, chunk = inflight.popleft()
+                ev, lives, chunk, gb = inflight.popleft()
                 ev.synchronize()
                 now = clock() - t0
                 finished = 0
-                for a in lives:
-                    a.done += chunk
-                    if a.done >= a.req.nsteps:
-                        self._finish(a, now, stats)
+                for i, a in enumerate(lives):
+                    a.inflight -= 1
+                    if a.failed is None:
+                        a.done += chunk
+                        if gb is not None:
+                            E = float(self.guard_host[gb, i])
+                            a.failed = energy_check(a.energy, E, self.growth_limit)
+                            if a.failed is None:
+                                a.energy = E
+                            else:
+                                active.remove(a)      # no further chunks
+                        if a.failed is None and a.done >= a.req.nsteps:
+                            self._finish(a, now, stats)
+                            used -= a.footprint
+                            active.remove(a)
+                            finished += 1
+                    if a.failed is not None and a.inflight == 0 and a.ws is not None:
+                        self._release_failed(a, now, stats)
                         used -= a.footprint
-                        active.remove(a)
                         finished += 1
                 if finished and progress is not None:
-                    progress(len(stats.results), total, now)
+                    progress(len(stats.results) + len(stats.failed), total, now)
             elif not inflight and not active:
                 if waiting:
                     sleep(0.001)

@@ -9,13 +9,16 @@ points, Ricker point force f0 = 5, t0 = 0.2, amp 1, direction z at
 scaling), upwind flux, four receivers recorded after every full step.
 
 Stored: the final modal coefficients of 256 elements (the source element,
-elements 0 and K-1, the four receivers' elements and a seeded sample), the
-total energy (Sec. 2 weighted norm) and the receiver traces.  Tests compare
-the GPU state on the stored elements at the quadrature points, element by
-element, and the energy and traces globally.
+elements 0 and K-1, the four receivers' elements and a seeded sample), their
+values at the Stroud quadrature points, the total energy (Sec. 2 weighted
+norm) and the receiver traces.  Tests compare the GPU state on the stored
+elements at the quadrature points, element by element, and the energy and
+traces globally; the benchmark reads the stored quadrature values.
 
 Calls only oracle/ and the input generators.  Run from the repository root:
     python tests/golden/long_run_n8_N4.py
+or, to add the quadrature values to an existing file without rerunning:
+    python tests/golden/long_run_n8_N4.py --quadrature-values
 """
 import os
 import sys
@@ -61,10 +64,24 @@ def main():
     rest = np.setdiff1d(np.arange(op.K), fixed)
     elems = np.sort(np.concatenate([fixed, rng.choice(rest, NSAMPLE - len(fixed), replace=False)]))
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "long_run_n8_N4.npz")
-    np.savez_compressed(out, elems=elems, c=c[elems], dt=dt, t=t, nsteps=NSTEPS, energy=op.energy(c),
-                        receivers=RECEIVERS, traces=traces)
+    np.savez_compressed(out, elems=elems, c=c[elems], fq=op.to_q(c[elems]), dt=dt, t=t, nsteps=NSTEPS,
+                        energy=op.energy(c), receivers=RECEIVERS, traces=traces)
     print("wrote", out, "dt", dt, "t", t, "energy", op.energy(c))
 
 
+def add_quadrature_values():
+    """Values at the quadrature points of the stored coefficients (the
+    oracle's modal-to-quadrature evaluation), added to the existing file."""
+    from oracle.reference import Reference
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "long_run_n8_N4.npz")
+    g = dict(np.load(out))
+    g["fq"] = Reference(N).to_q(g["c"])
+    np.savez_compressed(out, **g)
+    print("added fq", g["fq"].shape, "to", out)
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--quadrature-values":
+        add_quadrature_values()
+    else:
+        main()

@@ -136,3 +136,36 @@ def test_served_requests_match_oracle(precision):
         err = op.l2_q(got - ref) / op.l2_q(ref)
         print("served", r.rid, "N", r.N, "K", op.K, "steps", r.nsteps, "rel_l2", f"{err:.3e}", flush=True)
         assert err <= tol
+
+
+def test_guard_stops_a_poisoned_request():
+    """One request's state is set to contain a NaN right after its admission
+    (from Python, through the binding).  The server's energy guard stops it
+    after its first chunk and frees its slot; the other requests finish, and
+    their states and traces equal bitwise those of a run without it."""
+    from paper_1711_01175_amd.serving import Server
+    rec = np.array([[0.1, 0.2, -0.3]])
+    reqs = request_stream(4, n_range=(3, 4), degrees=(2, 3), nsteps=12, seed0=130)
+    for r in reqs:
+        r.receivers = rec
+    bad = reqs[2].rid
+
+    def poison(rid, ctx):
+        if rid == bad:
+            q = torch.zeros((ctx.K, 9, ctx.Np), dtype=ctx.torch_dtype, device="cuda")
+            q[ctx.K // 2, 4, 0] = float("nan")
+            ctx.set_state(q, 0.0)
+
+    srv = Server(budget_bytes=1 << 34, slots=4, precision=32, chunk_steps=3, keep_state=True)
+    stats = srv.run(reqs, on_admit=poison)
+    print(stats.summary(), [(f.rid, f.reason, f.steps_done) for f in stats.failed], flush=True)
+    assert [f.rid for f in stats.failed] == [bad]
+    assert stats.failed[0].reason == "non-finite energy" and stats.failed[0].steps_done == 3
+    assert sorted(r.rid for r in stats.results) == sorted(r.rid for r in reqs if r.rid != bad)
+    clean = Server(budget_bytes=1 << 34, slots=4, precision=32, chunk_steps=3, keep_state=True)
+    ref = {x.rid: x for x in clean.run([Request(r.rid, r.n, r.N, r.nsteps, r.xs, r.phases, r.amps, 0.0,
+                                                r.direction, r.f0, r.t0, rec) for r in reqs if r.rid != bad]).results}
+    for x in stats.results:
+        assert np.array_equal(x.state, ref[x.rid].state)
+        assert np.array_equal(x.traces, ref[x.rid].traces)
+        assert np.isfinite(x.energy)

@@ -26,3 +26,17 @@ def test_request_stream_is_seeded_and_poisson():
     gaps = np.diff([r.arrival for r in a])
     assert np.all(gaps >= 0) and abs(gaps.mean() - 0.1) < 0.05
     assert [r.arrival for r in request_stream(8)] == [0.0] * 8
+
+
+def test_energy_guard_decisions():
+    """A request is stopped when its energy is NaN or infinite, or grows by
+    more than the limit within one chunk once it is positive; growth from
+    zero (the source switching on) and ordinary growth pass."""
+    from paper_1711_01175_amd.serving import energy_check
+    assert energy_check(0.0, 1e-20, 1e6) is None
+    assert energy_check(1e-20, 1e-16, 1e6) is None
+    assert energy_check(1.0, 1e6, 1e6) is None
+    assert "grew" in energy_check(1.0, 1.0000001e6, 1e6)
+    assert energy_check(1.0, float("nan"), 1e6) == "non-finite energy"
+    assert energy_check(0.0, float("inf"), 1e6) == "non-finite energy"
+    assert energy_check(1.0, 1e30, None) is None
