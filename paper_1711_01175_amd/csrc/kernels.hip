@@ -92,6 +92,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   constexpr int RT = TL::RT, QT = TL::QT, NW = TL::NW, NT = TL::NT;
   constexpr int SV = TL::SV, SE = TL::SE, SF = TL::SF, SQ = TL::SQ;
   constexpr int KD = NpK / 4, KF = NfpK / 4;       // k-steps of the node / face contractions
+  // Operator fragments of the node contractions are held in groups of GK
+  // k-steps, two groups at a time, where all KD would crowd the registers
+  // (N = 7: 30 k-steps).
+  constexpr int GK = KD > 16 ? 10 : KD, NGK = (KD + GK - 1) / GK;
   constexpr int FPT = (Nfp * E + NT - 1) / NT;      // face points per thread and face
   __shared__ T sX[TL::X];
   __shared__ T sY[TL::Y];
@@ -127,20 +131,31 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // looked up once per tile (connectivity, then the node table), packed as
   // nb * 256 + nn, so a face's gather issues its data loads with no
   // dependent address loads in between.
-  int gofs[FPT][4];
+  // (Where the own stresses do not fit in LDS, N >= 5, the registers are
+  // short: there each gather looks its neighbour up itself.)
+  // The own volume node of each face point (four faces, one byte each) is
+  // looked up at the same time: a face's flux then issues no table load,
+  // which would otherwise wait behind the gathers already in flight.
+  constexpr bool PRE = SIGL;
+  int gofs[PRE ? FPT : 1][4];
+  int ilp[PRE ? FPT : 1];
+  if constexpr (PRE) {
 #pragma unroll
-  for (int p = 0; p < FPT; ++p) {
-    const int x = tid + p * NT;
-    const int xc = x < Nfp * E ? x : Nfp * E - 1;
-    const int e = xc / Nfp, j = xc % Nfp;
-    const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
-    const int4 wd = *reinterpret_cast<const int4*>(a.conn + ge * 4);
-    const int w4[4] = {wd.x, wd.y, wd.z, wd.w};
+    for (int p = 0; p < FPT; ++p) {
+      const int x = tid + p * NT;
+      const int xc = x < Nfp * E ? x : Nfp * E - 1;
+      const int e = xc / Nfp, j = xc % Nfp;
+      const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+      const int4 wd = *reinterpret_cast<const int4*>(a.conn + ge * 4);
+      const int w4[4] = {wd.x, wd.y, wd.z, wd.w};
+      ilp[p] = 0;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int code = w4[f] & 31;
-      const int nn = a.nbrnode[((f * 4 + code / 6) * 6 + code % 6) * Nfp + j];
-      gofs[p][f] = (w4[f] >> 5) * 256 + nn;
+      for (int f = 0; f < 4; ++f) {
+        const int code = w4[f] & 31;
+        const int nn = a.nbrnode[((f * 4 + code / 6) * 6 + code % 6) * Nfp + j];
+        gofs[p][f] = (w4[f] >> 5) * 256 + nn;
+        ilp[p] |= a.fmask[f * Nfp + j] << (8 * f);
+      }
     }
   }
   auto gather = [&](int f, FacePt<T>* pf) {
@@ -149,8 +164,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const int x = tid + p * NT;
       const int e = x / Nfp, j = x % Nfp;   // element-major: lanes share a neighbour's cache lines
       if (x < Nfp * E && e0 + e < Ke) {
-        const int nb = gofs[p][f] >> 8;
-        const int nn = gofs[p][f] & 255;
+        int nb, nn;
+        if constexpr (PRE) {
+          nb = gofs[p][f] >> 8;
+          nn = gofs[p][f] & 255;
+        } else {
+          const int32_t wd = a.conn[(e0 + e) * 4 + f];
+          const int code = wd & 31;
+          nb = wd >> 5;
+          nn = a.nbrnode[((f * 4 + code / 6) * 6 + code % 6) * Nfp + j];
+        }
         const T* qn = a.qin + nb * 9 * Np + nn;
         const T* sn = a.sin + nb * 6 * Np + nn;
         if constexpr (!SIGL) {
@@ -245,12 +268,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   const T* gl = &sgeo[lr * 32];   // geometry of this lane's element
 #pragma unroll 1
   for (int k = 0; k < 3; ++k) {
-    T af[KD];
-    if (own) {
-      const T* D = a.Dpad + ((k * RT + R) * KD) * 64 + l;
+    T afA[GK], afB[GK];
+    const T* D = a.Dpad + ((k * RT + R) * KD) * 64 + l;
+    auto frag_load = [&](const T* src, int g, T* dst) {
 #pragma unroll
-      for (int kk = 0; kk < KD; ++kk) af[kk] = D[kk * 64];
-    }
+      for (int u = 0; u < GK; ++u) dst[u] = (g * GK + u < KD) ? src[(g * GK + u) * 64] : T(0);
+    };
+    if (own) frag_load(D, 0, afA);
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
       const int x = tid + p * NT;
@@ -279,13 +303,20 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) gv[c] = acc_t{0, 0, 0, 0};
 #pragma unroll
-      for (int kk = 0; kk < KD; ++kk) {
-        const int rr = 4 * kk + lg;
-        const int row = rr * SV + (lr ^ sw(rr));
+      for (int g = 0; g < NGK; ++g) {
+        T* af = (g & 1) ? afB : afA;
+        if (g + 1 < NGK) frag_load(D, g + 1, (g & 1) ? afA : afB);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          rhs[c] = M::mma(af[kk], SG[row + c * 16], rhs[c]);
-          gv[c] = M::mma(af[kk], Sv[row + c * 16], gv[c]);
+        for (int u = 0; u < GK; ++u) {
+          const int kk = g * GK + u;
+          if (kk >= KD) break;
+          const int rr = 4 * kk + lg;
+          const int row = rr * SV + (lr ^ sw(rr));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            rhs[c] = M::mma(af[u], SG[row + c * 16], rhs[c]);
+            gv[c] = M::mma(af[u], Sv[row + c * 16], gv[c]);
+          }
         }
       }
       // d v_c / d x_m += (dr_k/dx_m) D_k v_c, symmetrised into the strain rows
@@ -325,7 +356,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         for (int c = 0; c < 9; ++c) fl[c * 16] = T(0);
         continue;
       }
-      const int il = a.fmask[f * Nfp + j];
+      int il;
+      if constexpr (PRE) il = (ilp[p] >> (8 * f)) & 255;
+      else il = a.fmask[f * Nfp + j];
       const T* gg = &sgeo[e * 32];
       const T n[3] = {gg[9 + f * 4 + 0], gg[9 + f * 4 + 1], gg[9 + f * 4 + 2]};
       const T fs = gg[9 + f * 4 + 3];
@@ -404,7 +437,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       const int i = R * 16 + M::row(lg, r);
       if (i < NpK) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Srv[i * SV + c * 16 + (lr ^ sw(i))] = rhs[c][r];
+        for (int c = 0; c < 3; ++c) Srv[i * SV + c * 16 + lr] = rhs[c][r];
 #pragma unroll
         for (int m = 0; m < 6; ++m) Ser[i * SE + m * 16 + lr] = rhs[3 + m][r];
       }
@@ -443,13 +476,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   auto wdot = [&](int p, const T* w, int j0, int n, T* o) {
     const int x = tid + p * NT;
     const int e = (x < E * Np ? x : E * Np - 1) / Np;
+    // (the velocity right-hand side is not swizzled: the lanes of a wave
+    // read at most a few distinct addresses here, served as broadcasts)
 #pragma unroll
     for (int u = 0; u < n; ++u) {
       const int j = j0 + u;
-      const int es = e ^ sw(j);
-      o[0] += w[u] * Srv[j * SV + es];
-      o[1] += w[u] * Srv[j * SV + 16 + es];
-      o[2] += w[u] * Srv[j * SV + 32 + es];
+      o[0] += w[u] * Srv[j * SV + e];
+      o[1] += w[u] * Srv[j * SV + 16 + e];
+      o[2] += w[u] * Srv[j * SV + 32 + e];
     }
   };
   // source, LSRK update and stores of pair p, given o[0..2] = W rhs_v
@@ -597,10 +631,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     }
     const int Rq = q0 / 16 + w;
     if (qrow && Rq < QT) {
-      T vf[KD];
+      T vfA[GK], vfB[GK];
       const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
 #pragma unroll
-      for (int kk = 0; kk < KD; ++kk) vf[kk] = Vr[kk * 64];
+      for (int u = 0; u < GK; ++u) vfA[u] = (u < KD) ? Vr[u * 64] : T(0);
       T lam[4], mu2[4];
       const bool ge_ok = e0 + lr < Ke;
 #pragma unroll
@@ -615,10 +649,21 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
       for (int m = 0; m < 6; ++m) ac[m] = acc_t{0, 0, 0, 0};
 #pragma unroll
-      for (int kk = 0; kk < KD; ++kk) {
-        const int row = (4 * kk + lg) * SE + lr;
+      for (int g = 0; g < NGK; ++g) {
+        T* vf = (g & 1) ? vfB : vfA;
+        if (g + 1 < NGK) {
+          T* nx = (g & 1) ? vfA : vfB;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) ac[m] = M::mma(vf[kk], Se[row + m * 16], ac[m]);
+          for (int u = 0; u < GK; ++u) nx[u] = ((g + 1) * GK + u < KD) ? Vr[((g + 1) * GK + u) * 64] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < GK; ++u) {
+          const int kk = g * GK + u;
+          if (kk >= KD) break;
+          const int row = (4 * kk + lg) * SE + lr;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) ac[m] = M::mma(vf[u], Se[row + m * 16], ac[m]);
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
