@@ -111,10 +111,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // stride SV and SF (both 16 mod 32 values): the element slot of row r is
   // e ^ (r mod 16).  The matrix-core reads (lanes over the elements of a few
   // rows) stay conflict-free, and the element-wise accesses (lanes over
-  // rows, one element) no longer fall into one or two banks.  N = 7 keeps
-  // the plain layout: there the extra index arithmetic raises the register
-  // spills (140 -> 252 bytes per lane) and costs 11 %.
-  auto sw = [](int r) { return N < 7 ? (r & 15) : 0; };
+  // rows, one element) no longer fall into one or two banks.  FP32 at N = 7
+  // keeps the plain layout: there the extra index arithmetic costs 10 % (the
+  // registers are full); FP64 at N = 7 gains 3 % from the swizzle.
+  auto sw = [](int r) { return (N < 7 || sizeof(T) == 8) ? (r & 15) : 0; };
   // own stresses [Np][SE] beside the face buffer, from the first volume
   // direction until the last flux, when they fit in the Y region
   constexpr bool SIGL = NfpK * SF + Np * SE <= TL::Y;
@@ -126,7 +126,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // (one face ahead where the own stresses come from global memory too:
   // there the second buffer would not fit in the registers)
   constexpr bool G2 = SIGL;
-  FacePt<T> pa[FPT], pb[G2 ? FPT : 1];
+  // Rounds of face points gathered ahead: all of them, except where the own
+  // stresses come from global memory and a second round holds only a few
+  // points (N = 7: 576 points on 512 threads); that round is gathered when
+  // its flux needs it.
+  constexpr int FPTP = (!SIGL && FPT > 1) ? 1 : FPT;
+  FacePt<T> pa[FPTP], pb[G2 ? FPTP : 1];
   // The neighbour element and node of every face point of this thread,
   // looked up once per tile (connectivity, then the node table), packed as
   // nb * 256 + nn, so a face's gather issues its data loads with no
@@ -158,9 +163,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       }
     }
   }
-  auto gather = [&](int f, FacePt<T>* pf) {
-#pragma unroll
-    for (int p = 0; p < FPT; ++p) {
+  auto gather_one = [&](int f, int p, FacePt<T>& pt) {
+    {
       const int x = tid + p * NT;
       const int e = x / Nfp, j = x % Nfp;   // element-major: lanes share a neighbour's cache lines
       if (x < Nfp * E && e0 + e < Ke) {
@@ -180,16 +184,20 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
           const int il = a.fmask[f * Nfp + j];
           const T* so = a.sin + (e0 + e) * 6 * Np + il;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) pf[p].sm[m] = so[m * Np];
+          for (int m = 0; m < 6; ++m) pt.sm[m] = so[m * Np];
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pf[p].vp[c] = qn[c * Np];
+        for (int c = 0; c < 3; ++c) pt.vp[c] = qn[c * Np];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) pf[p].sp[m] = sn[m * Np];
-        pf[p].zp = a.Z[nb * 2];
-        pf[p].zs = a.Z[nb * 2 + 1];
+        for (int m = 0; m < 6; ++m) pt.sp[m] = sn[m * Np];
+        pt.zp = a.Z[nb * 2];
+        pt.zs = a.Z[nb * 2 + 1];
       }
     }
+  };
+  auto gather = [&](int f, FacePt<T>* pf) {
+#pragma unroll
+    for (int p = 0; p < FPTP; ++p) gather_one(f, p, pf[p]);
   };
 
   // ---- element data: geometry, velocities (B layout) and, where they fit,
@@ -365,17 +373,20 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       T vm[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) vm[c] = Sv[il * SV + c * 16 + (e ^ sw(il))];
+      FacePt<T> late;
+      if (p >= FPTP) gather_one(f, p, late);
+      const FacePt<T>& pt = p < FPTP ? pf[p < FPTP ? p : 0] : late;
       T smv[6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) smv[m] = SIGL ? Ssig[il * SE + m * 16 + e] : pf[p].sm[m];
+      for (int m = 0; m < 6; ++m) smv[m] = SIGL ? Ssig[il * SE + m * 16 + e] : pt.sm[m];
       const T* sm = smv;
-      const T* sp = pf[p].sp;
+      const T* sp = pt.sp;
       const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2], sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
                        sm[4] * n[0] + sm[3] * n[1] + sm[2] * n[2]};
       const T Tp[3] = {sp[0] * n[0] + sp[5] * n[1] + sp[4] * n[2], sp[5] * n[0] + sp[1] * n[1] + sp[3] * n[2],
                        sp[4] * n[0] + sp[3] * n[1] + sp[2] * n[2]};
       T dT[3], dv[3];
-      interface_state(n, vm, Tm, pf[p].vp, Tp, gg[25], pf[p].zp, gg[26], pf[p].zs, dT, dv);
+      interface_state(n, vm, Tm, pt.vp, Tp, gg[25], pt.zp, gg[26], pt.zs, dT, dv);
       fl[0 * 16] = fs * dT[0];
       fl[1 * 16] = fs * dT[1];
       fl[2 * 16] = fs * dT[2];
@@ -582,9 +593,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   T* Sq = sY;  // [QC][SQ]
   constexpr int QC = TL::QC, NQC = (QT * 16 + QC - 1) / QC, KQ = QC / 4;
   // each chunk has QC/16 <= NW quadrature row tiles, so a wave takes at most
-  // one per chunk: row tile c QC/16 + w of chunk c, if w < QC/16
+  // one per chunk: row tile c QC/16 + w of chunk c, if w < QC/16.  With at
+  // least twice as many waves (8 waves, N = 5, 7) each row tile is split in
+  // two items, its diagonal stresses (with the trace) and its shear
+  // stresses, so every wave has one: row tile c QC/16 + w/2, half w % 2.
   static_assert(QC / 16 <= NW, "one quadrature row tile per wave and chunk");
-  const bool qrow = w < QC / 16;
+  constexpr bool SPLIT = NW >= 2 * (QC / 16) && N == 7 && sizeof(T) == 4;
+  constexpr int MC = SPLIT ? 3 : 6;            // stress components per item
+  const int slot = SPLIT ? (w >> 1) : w;
+  const int half = SPLIT ? (w & 1) : 0;
+  const bool qrow = slot < QC / 16;
   // lambda and 2 mu at this lane's four rows of quadrature row tile Rq
   // (clamped loads; rows past Nq and elements past K are zeroed after)
   auto lm_load = [&](int Rq, T* lam, T* mu2) {
@@ -613,7 +631,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // the first chunk's lambda, mu: issued before the barrier that ends the
   // update, in flight while the other waves finish it
   T lamN[4], muN[4];
-  if (qrow && w < QT) lm_load(w, lamN, muN);
+  if (qrow && slot < QT) lm_load(slot, lamN, muN);
   __syncthreads();
   acc_t pq[6];
 #pragma unroll
@@ -629,7 +647,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
       for (int u = 0; u < KQ; ++u) pf2[u] = (4 * u < rows) ? Pr[u * 64] : T(0);
     }
-    const int Rq = q0 / 16 + w;
+    const int Rq = q0 / 16 + slot;
     if (qrow && Rq < QT) {
       T vfA[GK], vfB[GK];
       const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
@@ -645,9 +663,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       }
       // the next chunk's lambda, mu, in flight during this chunk
       if (Rq + QC / 16 < QT) lm_load(Rq + QC / 16, lamN, muN);
-      acc_t ac[6];
+      acc_t ac[MC];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) ac[m] = acc_t{0, 0, 0, 0};
+      for (int m = 0; m < MC; ++m) ac[m] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int g = 0; g < NGK; ++g) {
         T* vf = (g & 1) ? vfB : vfA;
@@ -660,23 +678,31 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         for (int u = 0; u < GK; ++u) {
           const int kk = g * GK + u;
           if (kk >= KD) break;
-          const int row = (4 * kk + lg) * SE + lr;
+          const int row = (4 * kk + lg) * SE + lr + 3 * half * 16;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) ac[m] = M::mma(vf[u], Se[row + m * 16], ac[m]);
+          for (int m = 0; m < MC; ++m) ac[m] = M::mma(vf[u], Se[row + m * 16], ac[m]);
         }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int q = Rq * 16 + M::row(lg, r);
         if (q >= NqK) continue;
-        const T ltr = lam[r] * (ac[0][r] + ac[1][r] + ac[2][r]);
         T* o = &Sq[(q - q0) * SQ + lr];
-        o[0] = mu2[r] * ac[0][r] + ltr;
-        o[16] = mu2[r] * ac[1][r] + ltr;
-        o[32] = mu2[r] * ac[2][r] + ltr;
-        o[48] = mu2[r] * ac[3][r];
-        o[64] = mu2[r] * ac[4][r];
-        o[80] = mu2[r] * ac[5][r];
+        if (!SPLIT || half == 0) {
+          const T ltr = lam[r] * (ac[0][r] + ac[1][r] + ac[2][r]);
+          o[0] = mu2[r] * ac[0][r] + ltr;
+          o[16] = mu2[r] * ac[1][r] + ltr;
+          o[32] = mu2[r] * ac[2][r] + ltr;
+        }
+        if constexpr (!SPLIT) {
+          o[48] = mu2[r] * ac[3 % MC][r];
+          o[64] = mu2[r] * ac[4 % MC][r];
+          o[80] = mu2[r] * ac[5 % MC][r];
+        } else if (half == 1) {
+          o[48] = mu2[r] * ac[0][r];
+          o[64] = mu2[r] * ac[1][r];
+          o[80] = mu2[r] * ac[2][r];
+        }
       }
     }
     __syncthreads();
