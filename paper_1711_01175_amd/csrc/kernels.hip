@@ -467,22 +467,6 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   // row, old residual and state) are issued before pair p is computed, from
   // clamped (valid) addresses, so one memory latency covers the whole step.
   constexpr int NQV = VL ? 6 : 9;        // state values read from global memory
-  auto upd_load = [&](int p, T* w, T* rv, T* qv) {
-    const int x = tid + p * NT;
-    const int xc = x < E * Np ? x : E * Np - 1;
-    const int e = xc / Np, i = xc % Np;
-    const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
-    const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
-#pragma unroll
-    for (int j = 0; j < Np; ++j) w[j] = Wm[j * Np];
-    const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
-    if constexpr (MODE != 0) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) rv[c] = a.out[base + c * Np];
-#pragma unroll
-      for (int c = 0; c < NQV; ++c) qv[c] = a.qin[base + (c + 9 - NQV) * Np];
-    }
-  };
   // o[0..2] += sum over j in [j0, j0 + n) of W_ij rhs_v[j]
   auto wdot = [&](int p, const T* w, int j0, int n, T* o) {
     const int x = tid + p * NT;
@@ -530,57 +514,34 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       }
     }
   };
-#ifndef EWDG_UPD_PIPE
-#define EWDG_UPD_PIPE 0
-#endif
-  if constexpr (EWDG_UPD_PIPE && Np <= 35) {
-    T wA[Np], rA[9], qA[NQV], wB[Np], rB[9], qB[NQV];
-    upd_load(0, wA, rA, qA);
+  // one pair at a time, the W row in chunks of CW values whose loads issue
+  // together (the rows of the larger degrees do not fit in the registers)
+  constexpr int CW = Np < EWDG_CW ? Np : EWDG_CW;
 #pragma unroll
-    for (int p = 0; p < NPU; ++p) {
-      if (p + 1 < NPU) {
-        if (p & 1) upd_load(p + 1, wA, rA, qA);
-        else upd_load(p + 1, wB, rB, qB);
-      }
-      T o[9] = {0, 0, 0};
-      if (p & 1) {
-        wdot(p, wB, 0, Np, o);
-        upd_finish(p, o, rB, qB);
-      } else {
-        wdot(p, wA, 0, Np, o);
-        upd_finish(p, o, rA, qA);
-      }
+  for (int p = 0; p < NPU; ++p) {
+    const int x = tid + p * NT;
+    const int xc = x < E * Np ? x : E * Np - 1;
+    const int e = xc / Np, i = xc % Np;
+    const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
+    const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
+    T rv[9], qv[NQV];
+    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rv[c] = a.out[base + c * Np];
+#pragma unroll
+      for (int c = 0; c < NQV; ++c) qv[c] = a.qin[base + (c + 9 - NQV) * Np];
     }
-  } else {
-    // one pair at a time, the W row in chunks of CW values whose loads issue
-    // together (the rows of the larger degrees do not fit in the registers)
-    constexpr int CW = Np < EWDG_CW ? Np : EWDG_CW;
+    const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
+    T o[9] = {0, 0, 0};
 #pragma unroll
-    for (int p = 0; p < NPU; ++p) {
-      const int x = tid + p * NT;
-      const int xc = x < E * Np ? x : E * Np - 1;
-      const int e = xc / Np, i = xc % Np;
-      const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
-      const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
-      T rv[9], qv[NQV];
-      if constexpr (MODE != 0) {
+    for (int j0 = 0; j0 < Np; j0 += CW) {
+      constexpr int n0 = CW;
+      T w[n0];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) rv[c] = a.out[base + c * Np];
-#pragma unroll
-        for (int c = 0; c < NQV; ++c) qv[c] = a.qin[base + (c + 9 - NQV) * Np];
-      }
-      const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
-      T o[9] = {0, 0, 0};
-#pragma unroll
-      for (int j0 = 0; j0 < Np; j0 += CW) {
-        constexpr int n0 = CW;
-        T w[n0];
-#pragma unroll
-        for (int u = 0; u < n0; ++u) w[u] = (j0 + u < Np) ? Wm[(j0 + u) * Np] : T(0);
-        wdot(p, w, j0, (Np - j0) < CW ? (Np - j0) : CW, o);
-      }
-      upd_finish(p, o, rv, qv);
+      for (int u = 0; u < n0; ++u) w[u] = (j0 + u < Np) ? Wm[(j0 + u) * Np] : T(0);
+      wdot(p, w, j0, (Np - j0) < CW ? (Np - j0) : CW, o);
     }
+    upd_finish(p, o, rv, qv);
   }
   if (MODE == 0) return;
 
@@ -593,10 +554,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   T* Sq = sY;  // [QC][SQ]
   constexpr int QC = TL::QC, NQC = (QT * 16 + QC - 1) / QC, KQ = QC / 4;
   // each chunk has QC/16 <= NW quadrature row tiles, so a wave takes at most
-  // one per chunk: row tile c QC/16 + w of chunk c, if w < QC/16.  With at
-  // least twice as many waves (8 waves, N = 5, 7) each row tile is split in
-  // two items, its diagonal stresses (with the trace) and its shear
+  // one per chunk: row tile c QC/16 + w of chunk c, if w < QC/16.  In FP32
+  // at N = 7 (8 waves, twice the row tiles of a chunk) each row tile is
+  // split in two items, its diagonal stresses (with the trace) and its shear
   // stresses, so every wave has one: row tile c QC/16 + w/2, half w % 2.
+  // (At N = 5 and in FP64 the split measured slower: the V_Q products of a
+  // row tile are then formed twice for half the Hooke work each.)
   static_assert(QC / 16 <= NW, "one quadrature row tile per wave and chunk");
   constexpr bool SPLIT = NW >= 2 * (QC / 16) && N == 7 && sizeof(T) == 4;
   constexpr int MC = SPLIT ? 3 : 6;            // stress components per item
@@ -731,32 +694,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     }
   }
   __syncthreads();
-#ifndef EWDG_STORE_BATCH
-#define EWDG_STORE_BATCH 0
-#endif
-  if constexpr (!EWDG_STORE_BATCH) {
 #pragma unroll 2
-    for (int x = tid; x < E * 6 * Np; x += NT) {
-      const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, i = rem % Np;
-      if (e0 + e < Ke) a.sout[static_cast<int64_t>(e0 + e) * 6 * Np + rem] = Ss[i * SE + m * 16 + e];
-    }
-  } else {
-    // all LDS reads first, then the stores
-    constexpr int NSO = (E * 6 * Np + NT - 1) / NT;
-    T so[NSO];
-#pragma unroll
-    for (int p = 0; p < NSO; ++p) {
-      const int x = tid + p * NT;
-      const int xc = x < E * 6 * Np ? x : E * 6 * Np - 1;
-      const int e = xc / (6 * Np), rem = xc % (6 * Np), m = rem / Np, i = rem % Np;
-      so[p] = Ss[i * SE + m * 16 + e];
-    }
-#pragma unroll
-    for (int p = 0; p < NSO; ++p) {
-      const int x = tid + p * NT;
-      const int e = x / (6 * Np), rem = x % (6 * Np);
-      if (x < E * 6 * Np && e0 + e < Ke) a.sout[static_cast<int64_t>(e0 + e) * 6 * Np + rem] = so[p];
-    }
+  for (int x = tid; x < E * 6 * Np; x += NT) {
+    const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, i = rem % Np;
+    if (e0 + e < Ke) a.sout[static_cast<int64_t>(e0 + e) * 6 * Np + rem] = Ss[i * SE + m * 16 + e];
   }
 }
 
