@@ -20,13 +20,16 @@ semi-discrete operator, which does not depend on the basis:
   trace condition (Sec. 2, eq. HDGeqn; Sec. 3, eq. iHDGtrace), generalised
   to different impedances on the two sides of a face;
 * the element-by-element explicit update of Sec. 4.3 with forward Euler
-  replaced by a five-stage low-storage Runge-Kutta scheme.
+  replaced by a five-stage low-storage Runge-Kutta scheme;
+* the implicit (theta-scheme) step of the same operator solved by iHDG-II
+  (Sec. 3, Algorithm 1; ihdg.py).
 
 Parity status: every function is pinned by tests under tests/ (exactness,
 closed-form energy rate, conservation, plane-wave convergence, symmetry,
 Runge-Kutta order conditions, receiver sampling time against an exact
-wave).  Absolute solution values of the large
-heterogeneous workloads are not printed in the paper and are pinned only
-through those properties.
+wave; for iHDG-II a Krylov solve of the global implicit system, the theta
+scheme's discrete energy identities and its order in time).  Absolute
+solution values of the large heterogeneous workloads are not printed in the
+paper and are pinned only through those properties.
 """
 
