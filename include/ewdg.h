@@ -269,6 +269,45 @@ int ewdg_forward_misfit(ewdg_ctx* ctx, double dt, int nsteps, const double* data
  * Synchronises. */
 int ewdg_adjoint_gradient(ewdg_ctx* ctx, double* g, void* qbar0);
 
+/* ---------------------------------------------------------- implicit step
+ * Locally implicit time stepping (Sec. 4.3): the theta scheme
+ *     (q^{m+1} - q^m)/dt = theta (L q^{m+1} + s^{m+1}) + (1 - theta)(L q^m + s^m)
+ * of the same semi-discrete operator as ewdg_rhs (theta = 1: implicit Euler,
+ * eq. implicitHDG of Sec. 4.3 written for this system; theta = 1/2:
+ * Crank-Nicolson), solved by iHDG-II (Sec. 3, Algorithm 1).  Each iteration
+ * solves every element's local equation (eq. iHDGlocal) with the interface
+ * state (the weighted trace of eq. iHDGtrace) formed from the element's new
+ * unknowns and its neighbours' previous iterate; elements are independent
+ * within an iteration.  The initial guess is q^m; the loop stops at the
+ * first iteration whose change ||q^k - q^{k-1}||_{L2(Omega)} (all nine
+ * fields) is below tol (Sec. 6.1, the criterion without exact solution).
+ *
+ * ewdg_implicit_workspace_bytes: size of a third caller-owned workspace,
+ * (K n^2 + 24 K Np) values of the run precision plus, in FP32, K n^2 FP64
+ * values (n = 9 Np rounded up to 16: at N = 4, n = 320, 0.4 MB FP32 or
+ * 0.8 MB FP64 per element for the stored local inverses) and 12 K bytes.
+ * ewdg_bind_implicit_workspace: binds it (256-byte aligned device memory,
+ * EWDG_ENOMEM if too small; after ewdg_bind_workspace; a new mesh or main
+ * workspace drops the binding) and colours the face-adjacency graph.
+ * ewdg_implicit_setup: forms B_k = I - theta dt A_k (A_k: the operator on the
+ * element's own unknowns, probed column by column through the explicit
+ * operator kernels) and inverts it in FP64 on the GPU; synchronises.  Needs
+ * the material; setting material again requires a new set-up.  EWDG_EINVAL
+ * if a pivot of the unpivoted elimination vanishes.
+ * ewdg_implicit_step: nsteps steps of the dt and theta of the set-up from the
+ * stored state and time (source and receivers as in ewdg_step), at most
+ * max_iters iterations per step; iters[n] (host, may be NULL) receives the
+ * iteration count of step n and change[n] (host, may be NULL) the final
+ * change.  A step that reaches max_iters keeps its last iterate (compare
+ * change with tol).  Synchronises once per iteration (the stopping test);
+ * in FP32, tol must lie above the rounding level of the state (about
+ * 1e-6 of its L2 norm).  ewdg_implicit_dt returns the set-up's dt and theta. */
+int ewdg_implicit_workspace_bytes(const ewdg_ctx* ctx, size_t* bytes);
+int ewdg_bind_implicit_workspace(ewdg_ctx* ctx, void* device_ptr, size_t bytes);
+int ewdg_implicit_setup(ewdg_ctx* ctx, double dt, double theta);
+int ewdg_implicit_step(ewdg_ctx* ctx, int nsteps, double tol, int max_iters, int* iters, double* change);
+int ewdg_implicit_dt(const ewdg_ctx* ctx, double* dt, double* theta);
+
 const char* ewdg_last_error(const ewdg_ctx* ctx);
 
 #ifdef __cplusplus

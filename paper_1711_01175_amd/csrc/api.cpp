@@ -11,6 +11,7 @@
 
 #include "adjdev.hpp"
 #include "dev.hpp"
+#include "impdev.hpp"
 #include "ewdg.h"
 #include "mesh.hpp"
 #include "refelem.hpp"
@@ -65,6 +66,12 @@ struct ewdg_ctx {
   int fwd_steps = 0;
   double fwd_dt = 0.0;
   std::vector<double> step_t;  // time at the start of every recorded step
+  // locally implicit (iHDG-II) step: its own workspace, the colour classes
+  // of the face-adjacency graph and the step the local inverses were made for
+  ImpDev im;
+  bool imp_bound = false, imp_ready = false;
+  double imp_dt = 0.0, imp_theta = 0.0;
+  std::vector<int> imp_cstart;  // members[imp_cstart[c] .. imp_cstart[c+1]) have colour c
   std::string err;
 
   ~ewdg_ctx() {
@@ -273,6 +280,8 @@ int ewdg_set_mesh(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* VXY
   c->has_material = false;
   c->adj_bound = false;
   c->fwd_done = false;
+  c->imp_bound = false;
+  c->imp_ready = false;
   c->d.K = K;
   return EWDG_OK;
 }
@@ -472,6 +481,7 @@ int ewdg_bind_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_receivers,
   c->adj_bound = false;
   c->fwd_done = false;
   c->has_material = false;
+  c->imp_ready = false;
   c->has_source = false;
   c->nr = 0;
   c->rec_count = 0;
@@ -507,6 +517,7 @@ int ewdg_set_material(ewdg_ctx* c, const double* rho, const double* lam, const d
   c->t = 0.0;
   c->has_material = true;
   c->fwd_done = false;
+  c->imp_ready = false;
   if (c->has_source) {
     if ((rc = c->hip(launch_source_vector(c->d, c->src_elem, c->stream), "source vector"))) return rc;
   }
@@ -1326,6 +1337,204 @@ int ewdg_adjoint_gradient(ewdg_ctx* c, double* g, void* qbar0) {
       return rc;
   }
   return c->hip(hipStreamSynchronize(c->stream), "adjoint sync");
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Locally implicit step: the theta scheme solved by iHDG-II (Sec. 3,
+// Algorithm 1; Sec. 4.3).
+namespace {
+
+size_t imp_layout(ewdg_ctx* c, char* base) {
+  const int64_t K = c->mesh.K;
+  const size_t Np = c->re.Np, ts = c->tsz();
+  const int nv = 9 * static_cast<int>(Np);
+  const int n = static_cast<int>(pad_to(nv, 16));
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  ImpDev& m = c->im;
+  m.nv = nv;
+  m.n = n;
+  const size_t mats = static_cast<size_t>(K) * n * n;
+  m.inv = take(mats * ts);
+  m.work = c->prec == 64 ? static_cast<double*>(m.inv) : reinterpret_cast<double*>(take(mats * 8));
+  m.b = take(static_cast<size_t>(K) * nv * ts);
+  m.L = take(static_cast<size_t>(K) * nv * ts);
+  m.s = take(static_cast<size_t>(K) * 6 * Np * ts);
+  m.members = reinterpret_cast<int32_t*>(take(static_cast<size_t>(K) * 4));
+  m.epart = reinterpret_cast<double*>(take(static_cast<size_t>(K) * 8));
+  m.norm2 = reinterpret_cast<double*>(take(8));
+  m.flag = reinterpret_cast<int32_t*>(take(4));
+  return off;
+}
+
+// Greedy colouring of the face-adjacency graph; members lists the elements
+// colour by colour, cstart[c] the first position of colour c.
+int colour_classes(const MeshData& m, std::vector<int32_t>& members, std::vector<int>& cstart) {
+  const int64_t K = m.K;
+  std::vector<int> col(K, -1);
+  int ncol = 0;
+  for (int64_t k = 0; k < K; ++k) {
+    unsigned used = 0;
+    for (int f = 0; f < 4; ++f) {
+      const int64_t nb = m.conn[k * 4 + f] >> 5;
+      if (nb == k) return EWDG_EMESH;
+      if (col[nb] >= 0 && col[nb] < 32) used |= 1u << col[nb];
+    }
+    int cc = 0;
+    while (used & (1u << cc)) ++cc;
+    col[k] = cc;
+    ncol = std::max(ncol, cc + 1);
+  }
+  cstart.assign(ncol + 1, 0);
+  for (int64_t k = 0; k < K; ++k) ++cstart[col[k] + 1];
+  for (int cc = 0; cc < ncol; ++cc) cstart[cc + 1] += cstart[cc];
+  members.assign(K, 0);
+  std::vector<int> at(cstart.begin(), cstart.end() - 1);
+  for (int64_t k = 0; k < K; ++k) members[at[col[k]]++] = static_cast<int32_t>(k);
+  return EWDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ewdg_implicit_workspace_bytes(const ewdg_ctx* c, size_t* bytes) {
+  if (int rc = need(c, true, false, false)) return rc;
+  if (!bytes) return EWDG_EINVAL;
+  ewdg_ctx tmp;
+  tmp.N = c->N;
+  tmp.prec = c->prec;
+  tmp.re.Np = c->re.Np;
+  tmp.mesh.K = c->mesh.K;
+  *bytes = imp_layout(&tmp, nullptr);
+  return EWDG_OK;
+}
+
+int ewdg_bind_implicit_workspace(ewdg_ctx* c, void* ptr, size_t bytes) {
+  if (int rc = need(c, true, true, false)) return c ? c->fail(rc, "bind the main workspace first") : rc;
+  if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
+    return c->fail(EWDG_EINVAL, "workspace must be a non-null 256-byte aligned device pointer");
+  if (bytes < imp_layout(c, nullptr)) return c->fail(EWDG_ENOMEM, "workspace smaller than ewdg_implicit_workspace_bytes");
+  imp_layout(c, static_cast<char*>(ptr));
+  std::vector<int32_t> members;
+  if (colour_classes(c->mesh, members, c->imp_cstart) != EWDG_OK)
+    return c->fail(EWDG_EMESH, "an element is its own face neighbour");
+  int rc;
+  if ((rc = upload(c, c->im.members, members.data(), members.size() * 4))) return rc;
+  c->imp_bound = true;
+  c->imp_ready = false;
+  return EWDG_OK;
+}
+
+int ewdg_implicit_setup(ewdg_ctx* c, double dt, double theta) {
+  if (int rc = need(c, true, true, true)) return c ? c->fail(rc, "implicit setup needs material") : rc;
+  if (!c->imp_bound) return c->fail(EWDG_ESTATE, "implicit setup needs ewdg_bind_implicit_workspace");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(theta > 0.0 && theta <= 1.0))
+    return c->fail(EWDG_EINVAL, "need dt > 0 and 0 < theta <= 1");
+  ImpDev& m = c->im;
+  const int64_t K = c->mesh.K;
+  const double thdt = theta * dt;
+  int rc;
+  c->imp_ready = false;
+  if ((rc = c->hip(launch_imp_identity(m.work, K, m.n, c->stream), "identity"))) return rc;
+  if ((rc = c->hip(launch_imp_zero(c->prec, m.b, K * m.nv, c->stream), "zero"))) return rc;
+  // column j of A_k for every element k of one colour class: the operator
+  // of the state that is the j-th unit value on every member of the class
+  StageCoef none;   // no source
+  for (size_t cc = 0; cc + 1 < c->imp_cstart.size(); ++cc) {
+    const int32_t* mem = m.members + c->imp_cstart[cc];
+    const int cnt = c->imp_cstart[cc + 1] - c->imp_cstart[cc];
+    for (int j = 0; j < m.nv; ++j) {
+      if ((rc = c->hip(launch_imp_probe(c->prec, m.b, mem, cnt, m.nv, j - 1, j, c->stream), "probe"))) return rc;
+      if ((rc = c->hip(launch_sigma(c->d, m.b, m.s, c->stream), "sigma"))) return rc;
+      if ((rc = c->hip(launch_stage(c->d, 0, m.b, m.s, nullptr, nullptr, m.L, none, c->stream), "operator")))
+        return rc;
+      if ((rc = c->hip(launch_imp_gather(c->prec, m.L, m.work, mem, cnt, m.nv, m.n, j, thdt, c->stream), "gather")))
+        return rc;
+    }
+    if ((rc = c->hip(launch_imp_probe(c->prec, m.b, mem, cnt, m.nv, m.nv - 1, -1, c->stream), "probe"))) return rc;
+  }
+  const int32_t zero = 0;
+  if ((rc = upload(c, m.flag, &zero, 4))) return rc;
+  if ((rc = c->hip(launch_imp_invert(m.work, K, m.n, m.flag, c->stream), "invert"))) return rc;
+  if (c->prec == 32) {
+    if ((rc = c->hip(launch_imp_to_float(m.work, static_cast<float*>(m.inv), K * m.n * m.n, c->stream), "convert")))
+      return rc;
+  }
+  int32_t flag = 0;
+  if ((rc = c->hip(hipMemcpyAsync(&flag, m.flag, 4, hipMemcpyDeviceToHost, c->stream), "flag copy"))) return rc;
+  if ((rc = c->hip(hipStreamSynchronize(c->stream), "implicit setup sync"))) return rc;
+  if (flag) return c->fail(EWDG_EINVAL, "a local matrix I - theta dt A_k has a vanishing pivot");
+  c->imp_dt = dt;
+  c->imp_theta = theta;
+  c->imp_ready = true;
+  return EWDG_OK;
+}
+
+int ewdg_implicit_step(ewdg_ctx* c, int nsteps, double tol, int max_iters, int* iters, double* change) {
+  if (int rc = need(c, true, true, true)) return rc;
+  if (!c->imp_ready) return c->fail(EWDG_ESTATE, "implicit step needs ewdg_implicit_setup (again after new material)");
+  if (nsteps < 0 || !(tol >= 0.0) || max_iters < 1) return EWDG_EINVAL;
+  if (c->nr > 0 && c->rec_count + nsteps > c->max_steps)
+    return c->fail(EWDG_ENOMEM, "receiver record capacity exceeded");
+  ImpDev& m = c->im;
+  const double dt = c->imp_dt, th = c->imp_theta;
+  int rc;
+  for (int n = 0; n < nsteps; ++n) {
+    void* q = c->d.q[c->cur];
+    // b = q^m + (1 - theta) dt (L q^m + s^m) + theta dt s^{m+1}
+    const void* Lm = nullptr;
+    if (th < 1.0) {
+      const StageCoef sc = coef(c, 0.0, 0.0, 0.0, c->t);
+      if ((rc = c->hip(launch_stage(c->d, 0, q, c->d.s[c->cur], nullptr, nullptr, m.L, sc, c->stream), "operator")))
+        return rc;
+      Lm = m.L;
+    }
+    const StageCoef next = coef(c, 0.0, 0.0, 0.0, c->t + dt);
+    if ((rc = c->hip(launch_imp_fixed(c->d, m, q, Lm, (1.0 - th) * dt, next.src_elem, th * dt * next.srcval, next.dir,
+                                      c->stream),
+                     "fixed part")))
+      return rc;
+    int it = 0;
+    double dq = 0.0;
+    const StageCoef none;
+    while (it < max_iters) {
+      if ((rc = c->hip(launch_sigma(c->d, q, m.s, c->stream), "sigma"))) return rc;
+      if ((rc = c->hip(launch_stage(c->d, 0, q, m.s, nullptr, nullptr, m.L, none, c->stream), "operator"))) return rc;
+      if ((rc = c->hip(launch_imp_iterate(c->d, m, q, th * dt, c->stream), "iterate"))) return rc;
+      double n2 = 0.0;
+      if ((rc = c->hip(hipMemcpyAsync(&n2, m.norm2, 8, hipMemcpyDeviceToHost, c->stream), "norm copy"))) return rc;
+      if ((rc = c->hip(hipStreamSynchronize(c->stream), "norm sync"))) return rc;
+      ++it;
+      dq = std::sqrt(std::max(n2, 0.0));
+      if (!std::isfinite(dq)) return c->fail(EWDG_EINVAL, "iHDG-II iteration produced a non-finite change");
+      if (dq < tol) break;
+    }
+    if (iters) iters[n] = it;
+    if (change) change[n] = dq;
+    // sigma_h of the new state, kept beside it for the explicit stepper
+    if ((rc = c->hip(launch_sigma(c->d, q, c->d.s[c->cur], c->stream), "sigma"))) return rc;
+    c->t = c->t + dt;
+    if (c->nr > 0) {
+      if ((rc = c->hip(launch_receivers(c->d, q, c->nr, c->rec_count, c->stream), "receivers"))) return rc;
+      ++c->rec_count;
+    }
+  }
+  return EWDG_OK;
+}
+
+int ewdg_implicit_dt(const ewdg_ctx* c, double* dt, double* theta) {
+  if (!c || !dt || !theta) return EWDG_EINVAL;
+  if (!c->imp_ready) return EWDG_ESTATE;
+  *dt = c->imp_dt;
+  *theta = c->imp_theta;
+  return EWDG_OK;
 }
 
 }  // extern "C"

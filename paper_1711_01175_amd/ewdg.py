@@ -74,6 +74,11 @@ SIGNATURES = {
     "ewdg_rhs_adjoint": [_c_p, _c_d, _c_p, _c_p, _c_p, _c_p],
     "ewdg_forward_misfit": [_c_p, _c_d, _c_i, _c_p, _P_d],
     "ewdg_adjoint_gradient": [_c_p, _c_p, _c_p],
+    "ewdg_implicit_workspace_bytes": [_c_p, ctypes.POINTER(_c_sz)],
+    "ewdg_bind_implicit_workspace": [_c_p, _c_p, _c_sz],
+    "ewdg_implicit_setup": [_c_p, _c_d, _c_d],
+    "ewdg_implicit_step": [_c_p, _c_i, _c_d, _c_i, _c_p, _c_p],
+    "ewdg_implicit_dt": [_c_p, _P_d, _P_d],
     "ewdg_last_error": [_c_p],
 }
 _RESTYPE = {"ewdg_last_error": ctypes.c_char_p}
@@ -131,6 +136,7 @@ class Context:
         self.precision = int(precision)
         self._ws = None
         self._adj_ws = None
+        self._imp_ws = None
         self._stream = int(stream or 0)
         h = _c_p()
         rc = self.lib.ewdg_create(self.N, self.precision, _c_p(stream), ctypes.byref(h))
@@ -167,6 +173,7 @@ class Context:
             self.h = None
         self._ws = None
         self._adj_ws = None
+        self._imp_ws = None
 
     def __del__(self):
         try:
@@ -359,6 +366,42 @@ class Context:
             self._check(self.lib.ewdg_energy_device(self.h, _ptr(out)), "energy_device")
 
     # -------------------------------------------------------------- adjoint
+    # ------------------------------------------------ locally implicit step
+    def implicit_workspace_bytes(self):
+        b = _c_sz()
+        self._check(self.lib.ewdg_implicit_workspace_bytes(self.h, ctypes.byref(b)), "implicit_workspace_bytes")
+        return b.value
+
+    def bind_implicit_workspace(self, buffer=None):
+        torch = _torch()
+        nbytes = self.implicit_workspace_bytes()
+        if buffer is None:
+            buffer = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        with self._ordered(buffer):
+            self._check(self.lib.ewdg_bind_implicit_workspace(self.h, _ptr(buffer),
+                                                              buffer.numel() * buffer.element_size()),
+                        "bind_implicit_workspace")
+        self._imp_ws = buffer
+        return buffer
+
+    def implicit_setup(self, dt, theta=1.0):
+        """Form and invert I - theta dt A_k for every element (synchronises)."""
+        self._check(self.lib.ewdg_implicit_setup(self.h, float(dt), float(theta)), "implicit_setup")
+
+    def implicit_step(self, nsteps, tol=1e-10, max_iters=1000):
+        """nsteps theta-scheme steps solved by iHDG-II; returns the iteration
+        count and the final L2 change of every step (numpy arrays)."""
+        iters = np.zeros(max(int(nsteps), 1), dtype=np.int32)
+        change = np.zeros(max(int(nsteps), 1), dtype=np.float64)
+        self._check(self.lib.ewdg_implicit_step(self.h, int(nsteps), float(tol), int(max_iters), _ptr(iters),
+                                                _ptr(change)), "implicit_step")
+        return iters[:nsteps], change[:nsteps]
+
+    def implicit_dt(self):
+        dt, th = _c_d(), _c_d()
+        self._check(self.lib.ewdg_implicit_dt(self.h, ctypes.byref(dt), ctypes.byref(th)), "implicit_dt")
+        return dt.value, th.value
+
     def adjoint_workspace_bytes(self, max_steps, checkpoint_every=50, overlapped=False):
         """Bytes of the adjoint workspace; overlapped=True adds the second
         segment buffer that lets the recomputation run on a second stream."""

@@ -71,6 +71,7 @@ int main(int argc, char** argv) {
       // state errors before a mesh
       size_t bytes = 0;
       CHECK(ewdg_workspace_bytes(c, 0, 0, &bytes) == EWDG_ESTATE);
+      CHECK(ewdg_implicit_workspace_bytes(c, &bytes) == EWDG_ESTATE);
       double dt = 0;
       CHECK(ewdg_cfl_dt(c, 0.5, &dt) == EWDG_ESTATE);
       CHECK(ewdg_step(c, 1e-3, 1) == EWDG_ESTATE);
@@ -107,6 +108,13 @@ int main(int argc, char** argv) {
           if (nb >= 0 && nb < K && g < 4) CHECK((conn[static_cast<size_t>(nb) * 4 + g] >> 5) == k);
         }
       CHECK(ewdg_workspace_bytes(c, 4, 100, &bytes) == EWDG_OK && bytes > 0);
+      size_t ib = 0;
+      CHECK(ewdg_implicit_workspace_bytes(c, &ib) == EWDG_OK && ib > bytes);
+      CHECK(ewdg_implicit_setup(c, 1e-3, 1.0) == EWDG_ESTATE);       // nothing bound
+      int its = 0;
+      CHECK(ewdg_implicit_step(c, 1, 1e-10, 10, &its, nullptr) == EWDG_ESTATE);
+      double idt = 0, ith = 0;
+      CHECK(ewdg_implicit_dt(c, &idt, &ith) == EWDG_ESTATE);
       size_t ab = 0;
       CHECK(ewdg_adjoint_workspace_bytes(c, 100, 10, &ab) == EWDG_ESTATE);   // no workspace bound
       // calls that need the workspace or the material
