@@ -381,6 +381,74 @@ def run_adjoint(check_fp64=True):
     return out
 
 
+def implicit_bytes_per_element(Np, b):
+    """Compulsory HBM bytes per element of one iHDG-II iteration's update
+    kernel: the stored local inverse (9 Np)^2 values, the fixed right-hand
+    side, the operator output and the state read, the state written."""
+    nv = 9 * Np
+    return nv * nv * b + 4 * nv * b
+
+
+def run_implicit(n=16, N=4, cfl=4.0, theta=0.5, nsteps=10):
+    """Locally implicit steps (Crank-Nicolson solved by iHDG-II) on the
+    heterogeneous cube of n^3 x 6 tets at degree N, both precisions: set-up
+    time, iterations per step, time per step and per iteration, the update
+    kernel's inverse stream per iteration, the cost of the same simulated time
+    with the explicit LSRK(5,4) path at CFL 0.5, and FP32 against FP64.
+    The state is first advanced explicitly to t = 0.2 (the source wavelet's
+    peak); the stopping tolerance is 1e-6 (FP32) or 1e-10 (FP64) of the
+    state's L2 norm."""
+    import torch
+    EToV, VXYZ, _ = build_workload(n, N)
+    J = _jacobians(VXYZ)
+    res, fq = {}, {}
+    for prec in (64, 32):
+        c = _context(prec, N, EToV, VXYZ)
+        wq = c.reference_operator(8)
+        dte = c.cfl_dt(0.5)
+        c.step(dte, int(round(0.2 / dte)))
+        # explicit stage time on the same context (20 steps)
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        c.step(dte, 20)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        stage_us = ev0.elapsed_time(ev1) * 1e3 / 100
+        c.bind_implicit_workspace()
+        dt = c.cfl_dt(cfl)
+        t0 = time.perf_counter()
+        c.implicit_setup(dt, theta)
+        setup_s = time.perf_counter() - t0
+        tol = (1e-6 if prec == 32 else 1e-10) * _l2q(c.eval_quadrature(), J, wq)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, change = c.implicit_step(nsteps, tol, 500)
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / nsteps
+        fq[prec] = c.eval_quadrature()
+        nit = float(np.mean(iters))
+        res[prec] = {"setup_s": round(setup_s, 3), "iterations_per_step": [int(x) for x in iters],
+                     "ms_per_step": round(step_s * 1e3, 3), "ms_per_iteration": round(step_s * 1e3 / nit, 4),
+                     "inverse_stream_GBs": round(implicit_bytes_per_element(c.Np, prec // 8) * c.K
+                                                 / (step_s / nit) / 1e9, 1),
+                     "explicit_stage_us": round(stage_us, 2),
+                     "explicit_ms_same_time": round(stage_us * 5 * dt / dte / 1e3, 3),
+                     "converged": bool(np.all(change < tol))}
+        K = c.K
+        c.close()
+        torch.cuda.empty_cache()
+        print(f"implicit leg FP{prec}: {res[prec]}", file=sys.stderr, flush=True)
+    rel = _l2q(fq[32] - fq[64], J, wq) / _l2q(fq[64], J, wq)
+    return {"workload": f"{n}^3 hexes x 6 = {K} tets, N={N}, smooth media, Ricker source; Crank-Nicolson "
+                        f"(theta={theta}) at CFL {cfl} ({cfl / 0.5:g} x the explicit step), {nsteps} steps from the "
+                        f"explicit state at t=0.2, solved by iHDG-II",
+            "fp32": res[32], "fp64": res[64], "rel_l2_fp32_vs_fp64": rel,
+            "update_kernel_bytes_per_iteration": {str(p): implicit_bytes_per_element(Np, p // 8) * K
+                                                  for p, Np in ((32, (N + 1) * (N + 2) * (N + 3) // 6),
+                                                                (64, (N + 1) * (N + 2) * (N + 3) // 6))}}
+
+
 def cpu_baseline(N, n_sample, seconds):
     """Time the FP64 oracle's RHS on a smaller mesh of the same workload
     (per-element work does not depend on the mesh size)."""
@@ -429,6 +497,9 @@ def main():
                     help="serve a reduced 64-request stream instead of the full 256-request one")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the 1000-step FP32/FP64 and oracle comparisons and the N=7 leg")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the locally implicit (iHDG-II) leg")
+    ap.add_argument("--implicit-only", action="store_true",
+                    help="run only the locally implicit leg and print its JSON (for profiling)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the FP32 adjoint leg and print its JSON (for profiling)")
     ap.add_argument("--probe-copy", action="store_true",
@@ -454,6 +525,9 @@ def main():
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": run_adjoint(check_fp64=False)}), flush=True)
+        return
+    if args.implicit_only:
+        print(json.dumps({"implicit": run_implicit()}), flush=True)
         return
     EToV, VXYZ, _ = build_workload(args.n, args.N)
     r32 = run_gpu(32, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)
@@ -526,6 +600,8 @@ def main():
         line["serving"] = run_serving(not args.serving_reduced)
     if not args.no_adjoint:
         line["adjoint"] = run_adjoint()
+    if not args.no_implicit:
+        line["implicit"] = run_implicit()
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(args.N, args.cpu_n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
