@@ -22,13 +22,17 @@ semi-discrete operator, which does not depend on the basis:
 * the element-by-element explicit update of Sec. 4.3 with forward Euler
   replaced by a five-stage low-storage Runge-Kutta scheme;
 * the implicit (theta-scheme) step of the same operator solved by iHDG-II
-  (Sec. 3, Algorithm 1; ihdg.py).
+  (Sec. 3, Algorithm 1; ihdg.py);
+* steady transport by upwind HDG on structured squares and cubes solved by
+  iHDG-II (Sec. 4.1, Sec. 6.1; transport.py).
 
 Parity status: every function is pinned by tests under tests/ (exactness,
 closed-form energy rate, conservation, plane-wave convergence, symmetry,
 Runge-Kutta order conditions, receiver sampling time against an exact
 wave; for iHDG-II a Krylov solve of the global implicit system, the theta
-scheme's discrete energy identities and its order in time).  Absolute
+scheme's discrete energy identities and its order in time; for transport
+the paper's printed iteration counts, the marching of Theorem 1, a direct
+solve, exactness on Q_p and the order of accuracy).  Absolute
 solution values of the large heterogeneous workloads are not printed in the
 paper and are pinned only through those properties.
 """
