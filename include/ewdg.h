@@ -308,6 +308,58 @@ int ewdg_implicit_setup(ewdg_ctx* ctx, double dt, double theta);
 int ewdg_implicit_step(ewdg_ctx* ctx, int nsteps, double tol, int max_iters, int* iters, double* change);
 int ewdg_implicit_dt(const ewdg_ctx* ctx, double* dt, double* theta);
 
+/* ------------------------------------------------------ steady transport
+ * The paper's transport setting (Sec. 4.1, Sec. 6.1 Table 1): beta . grad u = f
+ * on the unit square (dim 2) or cube (dim 3), u = g on the inflow boundary,
+ * constant beta with nonzero components, a uniform grid of n^dim squares or
+ * cubes, degree p in 1..4 (tensor-product space Q_p), upwind HDG (the trace
+ * eliminated as in Sec. 4.1), solved by iHDG-II: each iteration solves every
+ * element's local equation with its inflow faces' exterior traces from the
+ * previous iterate (Theorem 1: the iteration marches the flow and is exact
+ * after finitely many iterations).  u^0 = 0.
+ *
+ * Numbering: element e = i_0 + n i_1 + n^2 i_2 (grid indices along x, y, z);
+ * volume points Q = q_0 + (p+3) q_1 + ... with q_a indexing the p+3 Gauss-
+ * Legendre points along axis a; face 2a + side (side 0: x_a low, 1: high),
+ * its points F indexing the Gauss points of the other axes in increasing
+ * order, first fastest.
+ *
+ * ewdg_transport_create: EWDG_EINVAL for unsupported dim, p, n, precision or
+ * a zero component of beta (dim values read).  Builds the reference
+ * operators on the host (FP64).
+ * ewdg_transport_sizes: E = n^dim elements, Np = (p+1)^dim coefficients,
+ * Nq = (p+3)^dim volume and Nqf = (p+3)^(dim-1) face points per element.
+ * ewdg_transport_points: physical points, host arrays xv [E][Nq][dim] and
+ * xf [E][2 dim][Nqf][dim] (either may be NULL).
+ * ewdg_transport_workspace_bytes / ewdg_transport_bind_workspace: caller-
+ * owned device memory (256-byte aligned), about E (4 Np b + 2 Nq 8 + 2 dim
+ * Nqf 8) bytes.
+ * ewdg_transport_set_problem: host arrays f [E][Nq], g [E][2 dim][Nqf] (read
+ * on the boundary inflow faces only) and, optionally, the exact solution ue
+ * [E][Nq].  Forms c_e = A^-1 ((f, phi)_e - boundary inflow) in FP64 on the
+ * GPU; synchronises.
+ * ewdg_transport_solve: iterates from u^0 = 0 until the stopping rule of Sec.
+ * 6.1 holds: with ue, | ||u^k - u^e|| - ||u^{k-1} - u^e|| | < tol (eq.
+ * tolerancecriteria), without it ||u^k - u^{k-1}|| < tol (L2 norms over the
+ * domain, the exact solution's by the volume-point rule), or max_iters.
+ * iters (host) receives k; history (host, max_iters + 1 values, may be NULL)
+ * the norm after every iteration, starting with ||u^0 - u^e|| (0 without
+ * ue).  One synchronisation per iteration.
+ * ewdg_transport_values: the last iterate at the volume points, host
+ * [E][Nq] FP64. */
+typedef struct ewdg_tr ewdg_tr;
+int ewdg_transport_create(int dim, int p, int n, const double* beta, int precision_bits, void* hip_stream,
+                          ewdg_tr** out);
+int ewdg_transport_destroy(ewdg_tr* tr);
+int ewdg_transport_sizes(const ewdg_tr* tr, int64_t* E, int* Np, int* Nq, int* Nqf);
+int ewdg_transport_points(const ewdg_tr* tr, double* xv, double* xf);
+int ewdg_transport_workspace_bytes(const ewdg_tr* tr, size_t* bytes);
+int ewdg_transport_bind_workspace(ewdg_tr* tr, void* device_ptr, size_t bytes);
+int ewdg_transport_set_problem(ewdg_tr* tr, const double* f, const double* g, const double* ue);
+int ewdg_transport_solve(ewdg_tr* tr, double tol, int max_iters, int* iters, double* history);
+int ewdg_transport_values(ewdg_tr* tr, double* u);
+const char* ewdg_transport_last_error(const ewdg_tr* tr);
+
 const char* ewdg_last_error(const ewdg_ctx* ctx);
 
 #ifdef __cplusplus

@@ -4,4 +4,4 @@ The compute path is the HIP library libewdg.so (C ABI in include/ewdg.h);
 this package holds its sources (csrc/), the build script and a thin ctypes
 binding (ewdg.Context).
 """
-from .ewdg import Context, EwdgError, batch_table_bytes, load, step_batch  # noqa: F401
+from .ewdg import Context, EwdgError, Transport, batch_table_bytes, load, step_batch  # noqa: F401

@@ -1,0 +1,46 @@
+// Device-side views and launchers of the steady transport solver (iHDG-II on
+// a structured grid of squares or cubes).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ewdg {
+
+// Elements are numbered e = i_0 + n i_1 + n^2 i_2.  Np = (p+1)^d modal
+// coefficients per element (orthonormal Legendre tensor basis), Nq = (p+3)^d
+// volume points and Nqf = (p+3)^(d-1) points per face.
+struct TrDev {
+  int d = 0, p = 0, n = 0, prec = 0, Np = 0, Nq = 0, Nqf = 0;
+  int64_t E = 0;
+  double J = 0, Jf = 0;                  // (h/2)^d, (h/2)^(d-1)
+  double bn[3] = {0, 0, 0};              // beta . n on the inflow face of each axis (< 0)
+  int in_side[3] = {0, 0, 0};            // inflow side of each axis (0: low, 1: high)
+  void* u[2] = {nullptr, nullptr};       // run precision [E][Np] iterates
+  void* c = nullptr;                     // run precision [E][Np] A^-1 (load - boundary inflow)
+  void* Gt = nullptr;                    // run precision [d][Np j][Np i] = (G_a)_ij, G_a = -A^-1 bn_a Jf C_a
+  double* uep = nullptr;                 // FP64 [E][Np] projection of the exact solution
+  double* Ainv = nullptr;                // FP64 [Np][Np]
+  double* Vq = nullptr;                  // FP64 [Nq][Np] basis at the volume points
+  double* Wq = nullptr;                  // FP64 [Nq] reference weights
+  double* Tf = nullptr;                  // FP64 [2d][Nqf][Np] basis on the face points (face 2a + side)
+  double* Wf = nullptr;                  // FP64 [Nqf]
+  double* fq = nullptr;                  // FP64 [E][Nq] staging of f
+  double* gq = nullptr;                  // FP64 [E][2d][Nqf] staging of g
+  double* ueq = nullptr;                 // FP64 [E][Nq] staging of the exact solution
+  double* rest = nullptr;                // FP64 [2][E] J ||u^e - projection||^2_K, J ||u^e||^2_K
+  double* epart = nullptr;               // FP64 [blocks] partial squared norms
+  double* scal = nullptr;                // FP64 [8]
+};
+
+hipError_t launch_tr_load(const TrDev& t, bool with_exact, hipStream_t st);
+// u[dst] = c + sum over inflow axes of G_a u[src](neighbour); scal[slot] =
+// sum over elements of J ||u[dst] - target||^2 with target = uep (to_exact)
+// or u[src].
+hipError_t launch_tr_sweep(const TrDev& t, int src, bool to_exact, int slot, hipStream_t st);
+hipError_t launch_tr_values(const TrDev& t, int src, double* out, hipStream_t st);
+hipError_t launch_tr_zero(const TrDev& t, int which, hipStream_t st);
+int tr_sweep_blocks(const TrDev& t);
+
+}  // namespace ewdg

@@ -79,9 +79,19 @@ SIGNATURES = {
     "ewdg_implicit_setup": [_c_p, _c_d, _c_d],
     "ewdg_implicit_step": [_c_p, _c_i, _c_d, _c_i, _c_p, _c_p],
     "ewdg_implicit_dt": [_c_p, _P_d, _P_d],
+    "ewdg_transport_create": [_c_i, _c_i, _c_i, _c_p, _c_i, _c_p, ctypes.POINTER(_c_p)],
+    "ewdg_transport_destroy": [_c_p],
+    "ewdg_transport_sizes": [_c_p, ctypes.POINTER(_c_i64), _P_i, _P_i, _P_i],
+    "ewdg_transport_points": [_c_p, _c_p, _c_p],
+    "ewdg_transport_workspace_bytes": [_c_p, ctypes.POINTER(_c_sz)],
+    "ewdg_transport_bind_workspace": [_c_p, _c_p, _c_sz],
+    "ewdg_transport_set_problem": [_c_p, _c_p, _c_p, _c_p],
+    "ewdg_transport_solve": [_c_p, _c_d, _c_i, _P_i, _c_p],
+    "ewdg_transport_values": [_c_p, _c_p],
+    "ewdg_transport_last_error": [_c_p],
     "ewdg_last_error": [_c_p],
 }
-_RESTYPE = {"ewdg_last_error": ctypes.c_char_p}
+_RESTYPE = {"ewdg_last_error": ctypes.c_char_p, "ewdg_transport_last_error": ctypes.c_char_p}
 
 _lib = None
 
@@ -526,3 +536,88 @@ def step_batch_static(contexts, dts, nsteps, stream=None):
         msgs = "; ".join(c.lib.ewdg_last_error(c.h).decode() for c in contexts
                          if c.lib.ewdg_last_error(c.h))
         raise EwdgError(rc, "step_batch_static " + msgs)
+
+
+class Transport:
+    """Steady transport beta . grad u = f on the unit square or cube, solved
+    by iHDG-II on the GPU (ewdg_transport_*); arrays as in include/ewdg.h."""
+
+    def __init__(self, dim, p, n, beta, precision=64, stream=None):
+        self.lib = load()
+        self.dim, self.p, self.n, self.precision = int(dim), int(p), int(n), int(precision)
+        b = np.zeros(3)
+        b[:self.dim] = np.asarray(beta, dtype=np.float64)[:self.dim]
+        h = _c_p()
+        rc = self.lib.ewdg_transport_create(self.dim, self.p, self.n, _ptr(b), self.precision, _c_p(stream),
+                                            ctypes.byref(h))
+        if rc != EWDG_OK:
+            raise EwdgError(rc, f"ewdg_transport_create(dim={dim}, p={p}, n={n}) failed")
+        self.h = h
+        E, Np, Nq, Nqf = _c_i64(), _c_i(), _c_i(), _c_i()
+        self._check(self.lib.ewdg_transport_sizes(self.h, ctypes.byref(E), ctypes.byref(Np), ctypes.byref(Nq),
+                                                  ctypes.byref(Nqf)), "sizes")
+        self.E, self.Np, self.Nq, self.Nqf = E.value, Np.value, Nq.value, Nqf.value
+        self._ws = None
+
+    def _check(self, rc, what=""):
+        if rc != EWDG_OK:
+            msg = self.lib.ewdg_transport_last_error(self.h) if getattr(self, "h", None) else b""
+            raise EwdgError(rc, f"{what} {msg.decode() if msg else ''}".strip())
+
+    def points(self):
+        """Volume points [E][Nq][dim] and face points [E][2 dim][Nqf][dim]."""
+        xv = np.zeros((self.E, self.Nq, self.dim))
+        xf = np.zeros((self.E, 2 * self.dim, self.Nqf, self.dim))
+        self._check(self.lib.ewdg_transport_points(self.h, _ptr(xv), _ptr(xf)), "points")
+        return xv, xf
+
+    def workspace_bytes(self):
+        b = _c_sz()
+        self._check(self.lib.ewdg_transport_workspace_bytes(self.h, ctypes.byref(b)), "workspace_bytes")
+        return b.value
+
+    def bind_workspace(self, buffer=None):
+        torch = _torch()
+        if buffer is None:
+            buffer = torch.empty(self.workspace_bytes(), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        self._check(self.lib.ewdg_transport_bind_workspace(self.h, _ptr(buffer), buffer.numel()), "bind_workspace")
+        self._ws = buffer
+        return buffer
+
+    def set_problem(self, f, g, ue=None):
+        f = _host(f, np.float64)
+        g = _host(g, np.float64)
+        if f.size != self.E * self.Nq or g.size != self.E * 2 * self.dim * self.Nqf:
+            raise EwdgError(EWDG_EINVAL, "f must be [E][Nq] and g [E][2 dim][Nqf]")
+        if ue is not None:
+            ue = _host(ue, np.float64)
+            if ue.size != self.E * self.Nq:
+                raise EwdgError(EWDG_EINVAL, "ue must be [E][Nq]")
+        self._check(self.lib.ewdg_transport_set_problem(self.h, _ptr(f), _ptr(g), _c_p(None) if ue is None
+                                                        else _ptr(ue)), "set_problem")
+
+    def solve(self, tol=1e-10, max_iters=100000):
+        """Returns (iterations, history) as in ewdg_transport_solve."""
+        it = _c_i()
+        hist = np.zeros(int(max_iters) + 1)
+        self._check(self.lib.ewdg_transport_solve(self.h, float(tol), int(max_iters), ctypes.byref(it),
+                                                  _ptr(hist)), "solve")
+        return it.value, hist[:it.value + 1]
+
+    def values(self):
+        out = np.zeros((self.E, self.Nq))
+        self._check(self.lib.ewdg_transport_values(self.h, _ptr(out)), "values")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ewdg_transport_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

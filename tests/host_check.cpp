@@ -136,6 +136,30 @@ int main(int argc, char** argv) {
   CHECK(ewdg_step_batch(nullptr, 0, nullptr, 1, nullptr, 0, nullptr) == EWDG_OK);
   CHECK(ewdg_step_batch_static(nullptr, 0, nullptr, 1, nullptr) == EWDG_OK);
   CHECK(ewdg_static_table_max_bytes(&tb) == EWDG_OK && tb == 256 * 1024);
+  // transport: reference operators of every supported (dim, p), points, errors
+  const double beta[3] = {1.0, -0.8, 0.6};
+  ewdg_tr* tr = nullptr;
+  CHECK(ewdg_transport_create(4, 2, 3, beta, 64, nullptr, &tr) == EWDG_EINVAL);
+  CHECK(ewdg_transport_create(2, 5, 3, beta, 64, nullptr, &tr) == EWDG_EINVAL);
+  for (int dim = 2; dim <= 3; ++dim)
+    for (int p = 1; p <= 4; ++p) {
+      tr = nullptr;
+      CHECK(ewdg_transport_create(dim, p, 2, beta, 32, nullptr, &tr) == EWDG_OK);
+      if (!tr) continue;
+      int64_t E = 0;
+      int Np = 0, Nq = 0, Nqf = 0;
+      CHECK(ewdg_transport_sizes(tr, &E, &Np, &Nq, &Nqf) == EWDG_OK && E == (dim == 2 ? 4 : 8));
+      std::vector<double> xv(static_cast<size_t>(E) * Nq * dim), xf(static_cast<size_t>(E) * 2 * dim * Nqf * dim);
+      CHECK(ewdg_transport_points(tr, xv.data(), xf.data()) == EWDG_OK);
+      for (double x : xv) CHECK(x > 0.0 && x < 1.0);
+      for (double x : xf) CHECK(x >= 0.0 && x <= 1.0);
+      size_t wb = 0;
+      CHECK(ewdg_transport_workspace_bytes(tr, &wb) == EWDG_OK && wb > 0);
+      int its = 0;
+      CHECK(ewdg_transport_solve(tr, 1e-10, 10, &its, nullptr) == EWDG_ESTATE);
+      CHECK(ewdg_transport_set_problem(tr, xv.data(), xv.data(), nullptr) == EWDG_ESTATE);
+      CHECK(ewdg_transport_destroy(tr) == EWDG_OK);
+    }
   if (failures) {
     std::fprintf(stderr, "%d checks failed\n", failures);
     return 1;

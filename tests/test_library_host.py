@@ -200,3 +200,35 @@ def test_empty_batch_and_null_arguments():
     assert lib.ewdg_adjoint_workspace_bytes(c.h, 10, 5, ctypes.byref(size)) == B.EWDG_ESTATE  # not bound
     assert lib.ewdg_adjoint_workspace_bytes_overlapped(c.h, 10, 5, ctypes.byref(size)) == B.EWDG_ESTATE
     assert lib.ewdg_adjoint_workspace_bytes_overlapped(None, 10, 5, ctypes.byref(size)) != B.EWDG_OK
+
+
+@pytest.mark.parametrize("d,p,n", [(2, 1, 3), (2, 4, 2), (3, 2, 2), (3, 4, 1)])
+def test_transport_points_follow_the_documented_numbering(d, p, n):
+    """The library's volume and face points, in the numbering include/ewdg.h
+    states, against the oracle's (an independent construction: numpy
+    Gauss-Legendre vs the library's Golub-Welsch)."""
+    from oracle.transport import Transport as OT
+    beta = (1.0, -0.8, 0.6)
+    T = P.Transport(d, p, n, beta)
+    o = OT(d, p, n, beta)
+    assert (T.E, T.Np, T.Nq, T.Nqf) == (n ** d, (p + 1) ** d, (p + 3) ** d, (p + 3) ** (d - 1))
+    xv, xf = T.points()
+    assert np.abs(xv - o.volume_points()).max() < 1e-15
+    for a in range(d):
+        for s in (0, 1):
+            assert np.abs(xf[:, 2 * a + s] - o.face_points(a, s)).max() < 1e-15
+    assert T.workspace_bytes() > 0
+
+
+def test_transport_rejects_bad_arguments():
+    for args in ((1, 2, 4, (1, 1, 1)), (2, 0, 4, (1, 1, 1)), (2, 5, 4, (1, 1, 1)), (3, 2, 0, (1, 1, 1)),
+                 (2, 2, 4, (1, 0, 1)), (3, 2, 4, (1, 1, 0))):
+        with pytest.raises(B.EwdgError):
+            P.Transport(*args)
+    with pytest.raises(B.EwdgError):
+        P.Transport(2, 2, 4, (1, 1), precision=16)
+    T = P.Transport(2, 2, 4, (1.0, 1.0))
+    with pytest.raises(B.EwdgError):      # no workspace, no problem
+        T.solve()
+    with pytest.raises(B.EwdgError):
+        T.set_problem(np.zeros((T.E, T.Nq)), np.zeros((T.E, 4, T.Nqf)))
