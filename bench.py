@@ -449,6 +449,57 @@ def run_implicit(n=16, N=4, cfl=4.0, theta=0.5, nsteps=10):
                                                                 (64, (N + 1) * (N + 2) * (N + 3) // 6))}}
 
 
+def run_transport(d=3, p=4, n=48):
+    """Steady transport (Sec. 4.1) by iHDG-II on n^d cubes of degree p, both
+    precisions: iterations (Theorem 1 predicts d (n - 1) + 2 with the stopping
+    rule of Sec. 6.1), time per iteration, the sweep's flop rate, FP32 against
+    FP64, and the counts of the Table 1 configurations."""
+    import paper_1711_01175_amd as P
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from test_oracle_transport import smooth, table1
+    ue, f, b = smooth(d)
+    res, vals, inputs = {}, {}, None
+    for prec in (64, 32):
+        T = P.Transport(d, p, n, b, precision=prec)
+        T.bind_workspace()
+        if inputs is None:
+            xv, xf = T.points()
+            inputs = (f(xv), ue(xf), ue(xv))
+            del xv, xf
+        t0 = time.perf_counter()
+        T.set_problem(*inputs)
+        setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        iters, hist = T.solve(1e-10, 10 * d * n)
+        el = time.perf_counter() - t0
+        vals[prec] = T.values()
+        flops = 2 * d * T.Np * T.Np * T.E
+        res[prec] = {"iterations": iters, "setup_s": round(setup, 3), "solve_s": round(el, 4),
+                     "ms_per_iteration": round(el / iters * 1e3, 4),
+                     "sweep_TFLOPs": round(flops / (el / iters) / 1e12, 2),
+                     "error_vs_exact": float(hist[-1])}
+        E, Np = T.E, T.Np
+        T.close()
+        print(f"transport leg FP{prec}: {res[prec]}", file=sys.stderr, flush=True)
+    del inputs
+    rel = float(np.linalg.norm(vals[32] - vals[64]) / np.linalg.norm(vals[64]))
+    counts = []
+    for dd, nn, pp, paper in table1():
+        ue2, f2, b2 = smooth(dd)
+        T = P.Transport(dd, pp, nn, b2, precision=64)
+        T.bind_workspace()
+        xv, xf = T.points()
+        T.set_problem(f2(xv), ue2(xf), ue2(xv))
+        counts.append([dd, nn, pp, paper, T.solve(1e-10, 1000)[0]])
+        T.close()
+    return {"workload": f"beta . grad u = f on the unit cube, beta = {tuple(b)}, smooth exact solution, {n}^{d} = "
+                        f"{E} cubes of degree {p} ({Np} modes), iHDG-II from zero, stopping rule with the exact "
+                        f"solution at 1e-10",
+            "predicted_iterations": d * (n - 1) + 2, "fp32": res[32], "fp64": res[64],
+            "rel_l2_fp32_vs_fp64_at_points": rel, "flops_per_iteration": 2 * d * Np * Np * E,
+            "table1_d_n_p_paper_ours": counts}
+
+
 def cpu_baseline(N, n_sample, seconds):
     """Time the FP64 oracle's RHS on a smaller mesh of the same workload
     (per-element work does not depend on the mesh size)."""
@@ -498,6 +549,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the 1000-step FP32/FP64 and oracle comparisons and the N=7 leg")
     ap.add_argument("--no-implicit", action="store_true", help="skip the locally implicit (iHDG-II) leg")
+    ap.add_argument("--no-transport", action="store_true", help="skip the steady transport (iHDG-II) leg")
+    ap.add_argument("--transport-only", action="store_true",
+                    help="run only the steady transport leg and print its JSON (for profiling)")
     ap.add_argument("--implicit-only", action="store_true",
                     help="run only the locally implicit leg and print its JSON (for profiling)")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -528,6 +582,9 @@ def main():
         return
     if args.implicit_only:
         print(json.dumps({"implicit": run_implicit()}), flush=True)
+        return
+    if args.transport_only:
+        print(json.dumps({"transport": run_transport()}), flush=True)
         return
     EToV, VXYZ, _ = build_workload(args.n, args.N)
     r32 = run_gpu(32, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)
@@ -602,6 +659,8 @@ def main():
         line["adjoint"] = run_adjoint()
     if not args.no_implicit:
         line["implicit"] = run_implicit()
+    if not args.no_transport:
+        line["transport"] = run_transport()
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(args.N, args.cpu_n, args.cpu_seconds)
     print(json.dumps(line), flush=True)

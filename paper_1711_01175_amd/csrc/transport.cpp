@@ -185,6 +185,7 @@ size_t tr_layout(ewdg_tr* T, char* base) {
   t.c = take(E * t.Np * ts);
   t.uep = reinterpret_cast<double*>(take(E * t.Np * 8));
   t.Gt = take(static_cast<size_t>(t.d) * t.Np * t.Np * ts);
+  t.Gfrag = take(static_cast<size_t>(t.d) * tr_row_tiles(t.Np) * tr_k_steps(t.Np) * 64 * ts);
   t.Ainv = reinterpret_cast<double*>(take(static_cast<size_t>(t.Np) * t.Np * 8));
   t.Vq = reinterpret_cast<double*>(take(static_cast<size_t>(t.Nq) * t.Np * 8));
   t.Wq = reinterpret_cast<double*>(take(static_cast<size_t>(t.Nq) * 8));
@@ -303,12 +304,28 @@ int ewdg_transport_bind_workspace(ewdg_tr* T, void* ptr, size_t bytes) {
   tr_layout(T, static_cast<char*>(ptr));
   const TrDev& t = T->t;
   int rc;
+  // G_a in matrix-core fragment order: lane l of block (a, R, kk) holds
+  // G_a[16 R + l % 16][4 kk + l / 16]
+  const int Np = t.Np, RT = tr_row_tiles(Np), KS = tr_k_steps(Np);
+  std::vector<double> frag(static_cast<size_t>(t.d) * RT * KS * 64, 0.0);
+  for (int a = 0; a < t.d; ++a)
+    for (int R = 0; R < RT; ++R)
+      for (int kk = 0; kk < KS; ++kk)
+        for (int l = 0; l < 64; ++l) {
+          const int i = 16 * R + l % 16, j = 4 * kk + l / 16;
+          if (i < Np && j < Np)
+            frag[((static_cast<size_t>(a) * RT + R) * KS + kk) * 64 + l] =
+                T->Gt[(static_cast<size_t>(a) * Np + j) * Np + i];
+        }
   if (T->t.prec == 32) {
-    std::vector<float> g(T->Gt.begin(), T->Gt.end());
+    std::vector<float> g(T->Gt.begin(), T->Gt.end()), gf(frag.begin(), frag.end());
     if ((rc = up(T, t.Gt, g.data(), g.size() * 4))) return rc;
+    if ((rc = up(T, t.Gfrag, gf.data(), gf.size() * 4))) return rc;
     if ((rc = T->hip(hipStreamSynchronize(T->stream), "upload sync"))) return rc;
   } else {
     if ((rc = up(T, t.Gt, T->Gt.data(), T->Gt.size() * 8))) return rc;
+    if ((rc = up(T, t.Gfrag, frag.data(), frag.size() * 8))) return rc;
+    if ((rc = T->hip(hipStreamSynchronize(T->stream), "upload sync"))) return rc;
   }
   if ((rc = up(T, t.Ainv, T->Ainv.data(), T->Ainv.size() * 8))) return rc;
   if ((rc = up(T, t.Vq, T->Vq.data(), T->Vq.size() * 8))) return rc;

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 
+#include "tiles.hpp"
 #include "trdev.hpp"
 
 namespace ewdg {
@@ -151,6 +152,105 @@ __global__ __launch_bounds__((TrSz<D, P>::NT)) void k_tr_sweep(TrDev t, int src,
   }
 }
 
+// The same sweep on the matrix cores (Np > 16): a workgroup takes EC = 16 CT
+// elements as matrix columns; U_new = C + sum_a G_a V_a with V_a the upwind
+// neighbours' coefficients (16x16x4 tiles: rows = output modes, k = input
+// modes, zero padded to 16 / 4).  The 4 waves own the row tiles round-robin;
+// each G_a fragment (one coalesced 64-lane load from L2) feeds CT products.
+// V_a sits in LDS in B-fragment order, so a fragment read is 64 consecutive
+// values; the result leaves through LDS in element-major rows.
+template <typename T>
+struct TrMmaShape {
+  static constexpr int CT = sizeof(T) == 4 ? 2 : 1;   // column tiles
+  static constexpr int EC = 16 * CT;                  // elements per workgroup
+};
+
+template <typename T, int D, int P>
+__global__ __launch_bounds__(256) void k_tr_sweep_mma(TrDev t, int src, int to_exact) {
+  using S = TrSz<D, P>;
+  using M = Mfma<T>;
+  using acc_t = typename M::acc_t;
+  constexpr int Np = S::Np, CT = TrMmaShape<T>::CT, EC = TrMmaShape<T>::EC;
+  constexpr int RT = (Np + 15) / 16, KS = (Np + 3) / 4, NpR = 16 * RT;
+  constexpr int VSZ = D * KS * CT * 64;        // B-fragment ordered neighbour values
+  constexpr int OSZ = EC * NpR;                // element-major result rows
+  __shared__ T V[VSZ > OSZ ? VSZ : OSZ];
+  __shared__ double red[4];
+  const T* uo = static_cast<const T*>(t.u[src]);
+  T* un = static_cast<T*>(t.u[1 - src]);
+  const T* c = static_cast<const T*>(t.c);
+  const T* G = static_cast<const T*>(t.Gfrag);
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * EC;
+  // gather: value j of element column col along axis a -> fragment slot
+  for (int x = tid; x < D * EC * 4 * KS; x += 256) {
+    const int j = x % (4 * KS), rest = x / (4 * KS), col = rest % EC, a = rest / EC;
+    const int64_t e = e0 + col;
+    T v = T(0);
+    if (j < Np && e < t.E) {
+      int64_t stride = 1;
+      for (int b = 0; b < a; ++b) stride *= t.n;
+      const int64_t ia = (e / stride) % t.n;
+      const int64_t nb = t.in_side[a] ? ia + 1 : ia - 1;
+      if (nb >= 0 && nb < t.n) v = uo[(e + (nb - ia) * stride) * Np + j];
+    }
+    V[(((a * KS + j / 4) * CT + col / 16) * 4 + j % 4) * 16 + col % 16] = v;
+  }
+  __syncthreads();
+  acc_t acc[(RT + 3) / 4][CT];
+#pragma unroll
+  for (int rr = 0; rr < (RT + 3) / 4; ++rr)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[rr][ct] = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int rr = 0; rr < (RT + 3) / 4; ++rr) {
+    const int R = w + 4 * rr;
+    if (R < RT) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const T* g = G + (static_cast<int64_t>(a * RT + R) * KS) * 64 + l;
+        const T* vb = V + a * KS * CT * 64 + l;
+#pragma unroll 8
+        for (int kk = 0; kk < KS; ++kk) {
+          const T av = g[kk * 64];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) acc[rr][ct] = M::mma(av, vb[(kk * CT + ct) * 64], acc[rr][ct]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // result rows to LDS: element col, mode i
+  const int lg = l / 16;
+#pragma unroll
+  for (int rr = 0; rr < (RT + 3) / 4; ++rr) {
+    const int R = w + 4 * rr;
+    if (R < RT) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) V[(ct * 16 + l % 16) * NpR + 16 * R + M::row(lg, r)] = acc[rr][ct][r];
+    }
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int x = tid; x < EC * Np; x += 256) {
+    const int col = x / Np, i = x % Np;
+    const int64_t e = e0 + col;
+    if (e < t.E) {
+      const T v = V[col * NpR + i] + c[e * Np + i];
+      un[e * Np + i] = v;
+      const double tg = to_exact ? t.uep[e * Np + i] : static_cast<double>(uo[e * Np + i]);
+      const double dd = static_cast<double>(v) - tg;
+      part += dd * dd;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off);
+  if (l == 0) red[w] = part;
+  __syncthreads();
+  if (tid == 0) t.epart[blockIdx.x] = t.J * (red[0] + red[1] + red[2] + red[3]);
+}
+
 __global__ __launch_bounds__(1024) void k_tr_sum(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
   __shared__ double red[1024];
   double acc = 0.0;
@@ -195,8 +295,14 @@ hipError_t launch_tr_load(const TrDev& t, bool with_exact, hipStream_t st) {
 template <typename T, int D, int P>
 static hipError_t sweep_impl(const TrDev& t, int src, bool to_exact, int slot, hipStream_t st) {
   using S = TrSz<D, P>;
-  const unsigned blocks = static_cast<unsigned>((t.E + S::EPB - 1) / S::EPB);
-  hipLaunchKernelGGL((k_tr_sweep<T, D, P>), dim3(blocks), dim3(S::NT), 0, st, t, src, to_exact ? 1 : 0);
+  unsigned blocks;
+  if constexpr (S::Np > 16) {
+    blocks = static_cast<unsigned>((t.E + TrMmaShape<T>::EC - 1) / TrMmaShape<T>::EC);
+    hipLaunchKernelGGL((k_tr_sweep_mma<T, D, P>), dim3(blocks), dim3(256), 0, st, t, src, to_exact ? 1 : 0);
+  } else {
+    blocks = static_cast<unsigned>((t.E + S::EPB - 1) / S::EPB);
+    hipLaunchKernelGGL((k_tr_sweep<T, D, P>), dim3(blocks), dim3(S::NT), 0, st, t, src, to_exact ? 1 : 0);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tr_sum, dim3(1), dim3(1024), 0, st, t.epart, static_cast<int64_t>(blocks), t.scal + slot);
@@ -220,9 +326,13 @@ hipError_t launch_tr_sweep(const TrDev& t, int src, bool to_exact, int slot, hip
   return t.d == 2 ? sweep_p<double, 2>(t, src, to_exact, slot, st) : sweep_p<double, 3>(t, src, to_exact, slot, st);
 }
 
+bool tr_uses_mma(int Np) { return Np > 16; }
+int tr_row_tiles(int Np) { return (Np + 15) / 16; }
+int tr_k_steps(int Np) { return (Np + 3) / 4; }
+
 int tr_sweep_blocks(const TrDev& t) {
   const int Np = t.Np;
-  const int epb = Np >= 256 ? 1 : 256 / Np;
+  const int epb = tr_uses_mma(Np) ? 16 : (Np >= 256 ? 1 : 256 / Np);   // the FP64 tile: the smaller count
   return static_cast<int>((t.E + epb - 1) / epb);
 }
 

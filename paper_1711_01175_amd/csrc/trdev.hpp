@@ -20,6 +20,8 @@ struct TrDev {
   void* u[2] = {nullptr, nullptr};       // run precision [E][Np] iterates
   void* c = nullptr;                     // run precision [E][Np] A^-1 (load - boundary inflow)
   void* Gt = nullptr;                    // run precision [d][Np j][Np i] = (G_a)_ij, G_a = -A^-1 bn_a Jf C_a
+  void* Gfrag = nullptr;                 // run precision [d][RT][KS][64]: G_a in 16x16x4 A-fragment order
+                                         // (lane l: row 16 R + l % 16, column 4 kk + l / 16; zero padded)
   double* uep = nullptr;                 // FP64 [E][Np] projection of the exact solution
   double* Ainv = nullptr;                // FP64 [Np][Np]
   double* Vq = nullptr;                  // FP64 [Nq][Np] basis at the volume points
@@ -42,5 +44,9 @@ hipError_t launch_tr_sweep(const TrDev& t, int src, bool to_exact, int slot, hip
 hipError_t launch_tr_values(const TrDev& t, int src, double* out, hipStream_t st);
 hipError_t launch_tr_zero(const TrDev& t, int which, hipStream_t st);
 int tr_sweep_blocks(const TrDev& t);
+// matrix-core sweep for Np > 16: row tiles and k-steps of the padded G_a
+int tr_row_tiles(int Np);
+int tr_k_steps(int Np);
+bool tr_uses_mma(int Np);
 
 }  // namespace ewdg
