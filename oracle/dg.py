@@ -67,12 +67,15 @@ def _double_dot(e6, s6):
 class Elastic:
     """The oracle operator L(q) for one mesh, degree and material."""
 
-    def __init__(self, N, VXYZ, rho_q, lam_q, mu_q, flux="upwind"):
+    def __init__(self, N, VXYZ, rho_q, lam_q, mu_q, flux="upwind", boundary=None):
         if flux not in ("upwind", "central"):
             raise ValueError(flux)
+        if boundary not in (None, "free", "absorbing"):
+            raise ValueError(boundary)
         self.flux = flux
+        self.bc = boundary
         self.ref = Reference(N)
-        self.mesh = Mesh(VXYZ)
+        self.mesh = Mesh(VXYZ, periodic=boundary is None)
         R, M = self.ref, self.mesh
         self.N, self.Np, self.Nq, self.K = N, R.Np, R.Nq, M.K
         if M.check_face_points(R.face_bary) > 1e-12:
@@ -103,12 +106,14 @@ class Elastic:
         self.Zs = np.sqrt(self.rho_bar * self.mu_bar)
         # Face evaluation tables.
         self.own_psi = np.stack([R.face_psi(FACE_VERTS[f]) for f in range(4)])  # [4][P][Np]
+        # neighbour face tables of the interior faces (boundary faces: -1)
         trip = M.nbr_verts.reshape(-1, 3)
-        keys = sorted({tuple(int(v) for v in t) for t in trip})
+        inner = ~M.boundary.reshape(-1)
+        keys = sorted({tuple(int(v) for v in t) for t in trip[inner]})
         self.combo_keys = keys
         self.combo_psi = np.stack([R.face_psi(k) for k in keys])                # [C][P][Np]
         lut = {k: i for i, k in enumerate(keys)}
-        self.combo = np.array([lut[tuple(int(v) for v in t)] for t in trip],
+        self.combo = np.array([lut[tuple(int(v) for v in t)] if ok else -1 for t, ok in zip(trip, inner)],
                               dtype=np.int64).reshape(self.K, 4)
         self.source = None
 
@@ -180,7 +185,17 @@ class Elastic:
             Tm[:, f] = np.einsum('kijp,kj->kpi', sig, n[:, f])
             nb = M.nbr[elems, f]
             cid = self.combo[elems, f]
-            for ci in np.unique(cid):
+            # boundary faces: the exterior state of the boundary condition
+            # (traction-free mirror v+ = v-, T+ = -T-; absorbing: zero)
+            bd = cid < 0
+            if np.any(bd):
+                if self.bc == "free":
+                    vp[bd, f] = vm[bd, f]
+                    Tp[bd, f] = -Tm[bd, f]
+                else:
+                    vp[bd, f] = 0.0
+                    Tp[bd, f] = 0.0
+            for ci in np.unique(cid[~bd]):
                 sel = np.nonzero(cid == ci)[0]
                 psin = self.combo_psi[ci]
                 kb = nb[sel]
@@ -206,7 +221,8 @@ class Elastic:
         if elems is None:
             elems = np.arange(self.K)
         elems = np.asarray(elems, dtype=np.int64)
-        U = np.unique(np.concatenate([elems, M.nbr[elems].ravel()]))
+        nbs = M.nbr[elems].ravel()
+        U = np.unique(np.concatenate([elems, nbs[nbs >= 0]]))
         pos = np.full(self.K, -1, dtype=np.int64)
         pos[U] = np.arange(len(U))
         s = self.sigma_h(c[U], U)                                # [U][6][Np]
@@ -220,7 +236,8 @@ class Elastic:
         # Face terms.
         vm, Tm, vp, Tp = self.face_traces(c, s, pos, elems)
         n = M.normal[elems][:, :, None, :]                        # [E][4][1][3]
-        nb = M.nbr[elems]
+        # impedances across a boundary face: the element's own
+        nb = np.where(M.boundary[elems], elems[:, None], M.nbr[elems])
         zpm = self.Zp[elems][:, None, None, None]
         zsm = self.Zs[elems][:, None, None, None]
         zpp = self.Zp[nb][:, :, None, None]
@@ -273,8 +290,14 @@ class Elastic:
 
     def face_dissipation(self, c):
         """Closed form of the energy rate under the interface states above:
-        each face point contributes -([T]^2 + Z^- Z^+ [v]^2)/(Z^- + Z^+) per
-        mode (normal with Z_p, tangential with Z_s), integrated over faces."""
+        each interior face point contributes -([T]^2 + Z^- Z^+ [v]^2)/(Z^- + Z^+)
+        per mode (normal with Z_p, tangential with Z_s), integrated over faces.
+
+        A boundary face adds the element's surface term v-.T* + v*.T- - v-.T-
+        with the boundary's exterior state: traction-free (T* = 0,
+        v* = v- - T-/Z per mode) gives -T^2/Z per mode; absorbing (zero
+        exterior: T* = (T- - Z v-)/2, v* = (v- - T-/Z)/2) gives
+        -(Z v^2 + T^2/Z)/2 per mode."""
         M = self.mesh
         elems = np.arange(self.K)
         pos = elems
@@ -295,8 +318,21 @@ class Elastic:
         dens = ((dTn ** 2 + zpm * zpp * dvn ** 2) / (zpm + zpp)
                 + (np.sum(dTt ** 2, -1) + zsm * zsp * np.sum(dvt ** 2, -1)) / (zsm + zsp))
         wts = M.area[:, :, None] * self.ref.face_w[None, None, :]
+        inner = ~M.boundary[:, :, None]
         # every interior face is visited from both sides
-        return float(-0.5 * np.sum(wts * dens))
+        total = -0.5 * np.sum(wts * dens * inner)
+        if np.any(M.boundary):
+            Tmn = np.sum(Tm * n, axis=-1)
+            Tmt = Tm - Tmn[..., None] * n
+            vmn = np.sum(vm * n, axis=-1)
+            vmt = vm - vmn[..., None] * n
+            if self.bc == "free":
+                bdens = Tmn ** 2 / zpm + np.sum(Tmt ** 2, -1) / zsm
+            else:
+                bdens = 0.5 * (zpm * vmn ** 2 + Tmn ** 2 / zpm + zsm * np.sum(vmt ** 2, -1)
+                               + np.sum(Tmt ** 2, -1) / zsm)
+            total -= np.sum(wts * bdens * M.boundary[:, :, None])
+        return float(total)
 
     def momentum(self, c):
         """Total momentum sum_K (rho v, 1)_Q."""

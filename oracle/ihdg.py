@@ -41,7 +41,7 @@ def greedy_colouring(nbr):
     for k in range(K):
         if np.any(nbr[k] == k):
             raise ValueError("element %d is its own neighbour" % k)
-        used = {int(colour[j]) for j in nbr[k] if colour[j] >= 0}
+        used = {int(colour[j]) for j in nbr[k] if j >= 0 and colour[j] >= 0}
         c = 0
         while c in used:
             c += 1

@@ -3,9 +3,10 @@
 Implements the mesh conventions of Sec. 2: elements K_j, the skeleton of
 faces, the outward normal n^- of an element and n^+ = -n^- of its neighbour.
 Faces are matched purely by the physical coordinates of their vertices,
-wrapped into the periodic box [-1,1)^3; the GPU library instead matches faces
-topologically from vertex ids.  Only fully periodic meshes are supported:
-every face must have exactly one partner.
+wrapped into the periodic box [-1,1)^3 (periodic meshes) or as they are
+(bounded meshes, where a face without a partner is a boundary face of the
+skeleton, the set of boundary faces of Sec. 2); the GPU library instead
+matches faces topologically from vertex ids.
 """
 import numpy as np
 
@@ -21,8 +22,14 @@ def _wrap_key(x):
     return tuple(int(v) for v in np.mod(k, int(_PERIOD * _GRID)))
 
 
+def _plain_key(x):
+    """Integer key of a point (no periodic wrap)."""
+    k = np.rint((x + 1.0) * _GRID).astype(np.int64)
+    return tuple(int(v) for v in k)
+
+
 class Mesh:
-    def __init__(self, VXYZ):
+    def __init__(self, VXYZ, periodic=True):
         X = np.asarray(VXYZ, dtype=np.float64)
         self.K = X.shape[0]
         self.X = X
@@ -35,6 +42,7 @@ class Mesh:
         # rk_x[k][i][j] = d r_i / d x_j
         self.rk_x = np.linalg.inv(self.A)
         self.volume = self.J * (4.0 / 3.0)
+        self.periodic = bool(periodic)
         self._faces()
         self._match()
 
@@ -64,7 +72,8 @@ class Mesh:
         """Find, for every (element, face), the neighbour element and the
         neighbour's local vertex numbers of our face's three vertices."""
         K = self.K
-        vkey = [[_wrap_key(self.X[k, i]) for i in range(4)] for k in range(K)]
+        key_of = _wrap_key if self.periodic else _plain_key
+        vkey = [[key_of(self.X[k, i]) for i in range(4)] for k in range(K)]
         table = {}
         for k in range(K):
             for f, tri in enumerate(FACE_VERTS):
@@ -74,7 +83,12 @@ class Mesh:
         self.nbr_face = np.full((K, 4), -1, dtype=np.int64)
         # nbr_verts[k][f] = neighbour-local vertex numbers matching FACE_VERTS[f]
         self.nbr_verts = np.full((K, 4, 3), -1, dtype=np.int64)
+        self.boundary = np.zeros((K, 4), dtype=bool)
         for key, lst in table.items():
+            if len(lst) == 1 and not self.periodic:
+                k1, f1 = lst[0]
+                self.boundary[k1, f1] = True
+                continue
             if len(lst) != 2:
                 raise ValueError("face without exactly one partner (mesh not periodic "
                                  "or not conforming)")
@@ -93,14 +107,17 @@ class Mesh:
         vertices, mapped to physical space.  Zero for a consistent matching."""
         err = 0.0
         for f, tri in enumerate(FACE_VERTS):
-            own = np.einsum('pm,kmd->kpd', bary, self.X[:, list(tri)])
-            nb = self.nbr[:, f]
-            nv = self.nbr_verts[:, f]
+            inner = ~self.boundary[:, f]
+            own = np.einsum('pm,kmd->kpd', bary, self.X[inner][:, list(tri)])
+            nb = self.nbr[inner, f]
+            nv = self.nbr_verts[inner, f]
             Xn = np.take_along_axis(self.X[nb], nv[:, :, None], axis=1)   # [K][3][3]
             other = np.einsum('pm,kmd->kpd', bary, Xn)
             d = other - own
-            d = d - _PERIOD * np.rint(d / _PERIOD)
-            err = max(err, float(np.abs(d).max()))
+            if self.periodic:
+                d = d - _PERIOD * np.rint(d / _PERIOD)
+            if d.size:
+                err = max(err, float(np.abs(d).max()))
         return err
 
     def locate(self, x, tol=1e-12):

@@ -1,4 +1,4 @@
-"""Periodic tetrahedral meshes of the cube [-1,1]^3.
+"""Periodic and bounded tetrahedral meshes of the cube [-1,1]^3.
 
 Each of the n^3 hexahedra of side h = 2/n is cut into six tetrahedra by the
 Kuhn (Freudenthal) split: for every permutation p of the three axes the
@@ -60,6 +60,17 @@ def kuhn_periodic_mesh(n, shuffle_seed=None):
     wrapped = lat % n
     EToV = wrapped[..., 0] + n * (wrapped[..., 1] + n * wrapped[..., 2])
     VXYZ = -1.0 + h * lat.astype(np.float64)
+    return EToV.astype(np.int64), VXYZ
+
+
+def kuhn_box_mesh(n, shuffle_seed=None):
+    """The same 6 n^3 Kuhn tetrahedra of [-1,1]^3 without the periodic wrap:
+    vertex ids index the (n+1)^3 lattice, so the faces on the box boundary
+    have no partner.  Element order and shapes as kuhn_periodic_mesh."""
+    _, VXYZ = kuhn_periodic_mesh(n, shuffle_seed=shuffle_seed)
+    h = 2.0 / n
+    lat = np.rint((VXYZ + 1.0) / h).astype(np.int64)
+    EToV = lat[..., 0] + (n + 1) * (lat[..., 1] + (n + 1) * lat[..., 2])
     return EToV.astype(np.int64), VXYZ
 
 
