@@ -84,6 +84,17 @@ int ewdg_set_stream(ewdg_ctx* ctx, void* hip_stream);
  * (EWDG_EINVAL before any array is read otherwise), e.g. K < 6.8 M at
  * N = 4 and K < 1.99 M at N = 7. */
 int ewdg_set_mesh(ewdg_ctx* ctx, int64_t K, const int64_t* EToV, const double* VXYZ);
+/* Bounded meshes (the boundary faces of the skeleton, Sec. 2): as
+ * ewdg_set_mesh, but faces without a partner are boundary faces with
+ * condition bc: EWDG_BC_FREE (traction-free: the exterior state is the
+ * mirror v+ = v-, T+ = -T-, so the interface state has zero traction) or
+ * EWDG_BC_ABSORBING (zero exterior state: the upwind state keeps only the
+ * outgoing characteristics).  EWDG_BC_PERIODIC is ewdg_set_mesh.  A boundary
+ * face's ewdg_connectivity entry names the element itself.  The stage,
+ * operator, energy, receivers and the implicit step support bounded meshes;
+ * batched stepping and the adjoint refuse them (EWDG_EINVAL). */
+enum { EWDG_BC_PERIODIC = 0, EWDG_BC_FREE = 1, EWDG_BC_ABSORBING = 2 };
+int ewdg_set_mesh_bc(ewdg_ctx* ctx, int64_t K, const int64_t* EToV, const double* VXYZ, int bc);
 
 /* Sizes of one element: nodes, face nodes, quadrature points. */
 int ewdg_sizes(const ewdg_ctx* ctx, int* Np, int* Nfp, int* Nq);

@@ -169,6 +169,8 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.nbrnode = reinterpret_cast<int32_t*>(take(96 * Nfp * 4));
   d.nbrface = reinterpret_cast<int32_t*>(take(96 * Nfp * 4));
   d.fmask = reinterpret_cast<int32_t*>(take(4 * Nfp * 4));
+  d.bcm_buf = reinterpret_cast<int32_t*>(take(K * 4));
+  d.bcm = (base && c->mesh.bc != 0) ? d.bcm_buf : nullptr;
   return off;
 }
 
@@ -260,7 +262,13 @@ int ewdg_set_stream(ewdg_ctx* c, void* s) {
 const char* ewdg_last_error(const ewdg_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 int ewdg_set_mesh(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* VXYZ) {
+  return ewdg_set_mesh_bc(c, K, EToV, VXYZ, EWDG_BC_PERIODIC);
+}
+
+int ewdg_set_mesh_bc(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* VXYZ, int bc) {
   if (!c || !EToV || !VXYZ) return EWDG_EINVAL;
+  if (bc != EWDG_BC_PERIODIC && bc != EWDG_BC_FREE && bc != EWDG_BC_ABSORBING)
+    return c->fail(EWDG_EINVAL, "unknown boundary condition");
   // the kernels index element data with 32-bit offsets and pack a
   // neighbour index with a node index into 32 bits (nbr * 256 + node)
   {
@@ -272,7 +280,7 @@ int ewdg_set_mesh(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* VXY
   }
   MeshData m;
   std::string e;
-  const int rc = build_mesh(K, EToV, VXYZ, m, e);
+  const int rc = build_mesh(K, EToV, VXYZ, m, e, bc);
   if (rc != EWDG_OK) return c->fail(rc, e);
   c->mesh = std::move(m);
   c->has_mesh = true;
@@ -477,6 +485,7 @@ int ewdg_bind_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_receivers,
     if ((rc = upload(c, c->d.nbrface, nbf.data(), nbf.size() * 4))) return rc;
   }
   if ((rc = upload(c, c->d.fmask, fm.data(), fm.size() * 4))) return rc;
+  if (m.bc != 0 && (rc = upload(c, c->d.bcm_buf, m.bcm.data(), m.bcm.size() * 4))) return rc;
   c->bound = true;
   c->adj_bound = false;
   c->fwd_done = false;
@@ -799,6 +808,8 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
   ewdg_batch_table_bytes(n, &need_b);
   if (table_bytes < need_b) return EWDG_ENOMEM;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i] && ctxs[i]->mesh.bc != 0) return ctxs[i]->fail(EWDG_EINVAL, "batched stepping needs periodic meshes");
   for (int i = 0; i < n; ++i) {
     ewdg_ctx* c = ctxs[i];
     if (!c) return EWDG_EINVAL;
@@ -987,6 +998,8 @@ int ewdg_step_batch_static(ewdg_ctx* const* ctxs, int n, const double* dts, int 
   ewdg_batch_table_bytes(n, &need_b);
   if (need_b > kStaticTableBytes)
     return ctxs[0]->fail(EWDG_ENOMEM, "batch too large for the static launch table (ewdg_static_table_max_bytes)");
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i] && ctxs[i]->mesh.bc != 0) return ctxs[i]->fail(EWDG_EINVAL, "batched stepping needs periodic meshes");
   for (int i = 0; i < n; ++i) {
     ewdg_ctx* c = ctxs[i];
     if (!c) return EWDG_EINVAL;
@@ -1152,6 +1165,7 @@ int ewdg_adjoint_workspace_bytes_overlapped(const ewdg_ctx* c, int max_steps, in
 
 int ewdg_bind_adjoint_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_steps, int checkpoint_every) {
   if (int rc = need(c, true, true, false)) return c ? c->fail(rc, "bind the forward workspace first") : rc;
+  if (c->mesh.bc != 0) return c->fail(EWDG_EINVAL, "the adjoint needs a periodic mesh");
   if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
     return c->fail(EWDG_EINVAL, "adjoint workspace must be a non-null 256-byte aligned device pointer");
   if (max_steps < 1 || checkpoint_every < 1) return c->fail(EWDG_EINVAL, "max_steps and checkpoint_every must be >= 1");
@@ -1382,6 +1396,7 @@ int colour_classes(const MeshData& m, std::vector<int32_t>& members, std::vector
   for (int64_t k = 0; k < K; ++k) {
     unsigned used = 0;
     for (int f = 0; f < 4; ++f) {
+      if (m.bc != 0 && ((m.bcm[k] >> (2 * f)) & 3)) continue;   // boundary face
       const int64_t nb = m.conn[k * 4 + f] >> 5;
       if (nb == k) return EWDG_EMESH;
       if (col[nb] >= 0 && col[nb] < 32) used |= 1u << col[nb];

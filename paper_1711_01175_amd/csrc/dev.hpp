@@ -61,6 +61,8 @@ struct Dev {
   int32_t* nbrnode = nullptr;        // [4][4][6][Nfp] neighbour volume node
   int32_t* nbrface = nullptr;        // [4][4][6][Nfp] neighbour face-local node
   int32_t* fmask = nullptr;          // [4][Nfp]
+  int32_t* bcm = nullptr;            // [K] boundary codes, 2 bits per face; null for periodic meshes
+  int32_t* bcm_buf = nullptr;        // its storage in the workspace
   // scratch for setup (aliases q[1], s[1], res while no state exists)
   void* scratch = nullptr;
   size_t scratch_bytes = 0;

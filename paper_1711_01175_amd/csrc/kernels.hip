@@ -37,6 +37,7 @@ struct StageArgs {
   T a, b, dt, srcval;
   T dir0, dir1, dir2;
   int64_t src_elem;
+  const int32_t* bcm;   // bounded meshes: per element, 2 bits per face (1 traction-free, 2 absorbing)
 };
 
 // Exact Riemann state per wave mode at one face point (outward normal n of
@@ -82,7 +83,7 @@ struct FacePt {
   T sm[6], vp[3], sp[6], zp, zs;
 };
 
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, bool BND = false>
 __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   using TL = Tile<N>;
   using M = Mfma<T>;
@@ -381,12 +382,28 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       for (int m = 0; m < 6; ++m) smv[m] = SIGL ? Ssig[il * SE + m * 16 + e] : pt.sm[m];
       const T* sm = smv;
       const T* sp = pt.sp;
+      const T* vp = pt.vp;
+      T spx[6], vpx[3];
+      if constexpr (BND) {
+        // a boundary face's gather read the element's own trace: the exterior
+        // state is its mirror (traction-free: v+ = v-, T+ = -T-) or zero
+        // (absorbing)
+        const int bcode = (a.bcm[e0 + e] >> (2 * f)) & 3;
+        const T cv = bcode == 2 ? T(0) : T(1);
+        const T cs = bcode == 0 ? T(1) : (bcode == 1 ? T(-1) : T(0));
+#pragma unroll
+        for (int m = 0; m < 6; ++m) spx[m] = cs * pt.sp[m];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vpx[c] = cv * pt.vp[c];
+        sp = spx;
+        vp = vpx;
+      }
       const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2], sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
                        sm[4] * n[0] + sm[3] * n[1] + sm[2] * n[2]};
       const T Tp[3] = {sp[0] * n[0] + sp[5] * n[1] + sp[4] * n[2], sp[5] * n[0] + sp[1] * n[1] + sp[3] * n[2],
                        sp[4] * n[0] + sp[3] * n[1] + sp[2] * n[2]};
       T dT[3], dv[3];
-      interface_state(n, vm, Tm, pt.vp, Tp, gg[25], pt.zp, gg[26], pt.zs, dT, dv);
+      interface_state(n, vm, Tm, vp, Tp, gg[25], pt.zp, gg[26], pt.zs, dT, dv);
       fl[0 * 16] = fs * dT[0];
       fl[1 * 16] = fs * dT[1];
       fl[2 * 16] = fs * dT[2];
@@ -701,11 +718,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   }
 }
 
-// One mesh: workgroups map to element tiles, XCD-contiguous.
-template <typename T, int N, int MODE>
+// One mesh: workgroups map to element tiles, XCD-contiguous.  BND: the mesh
+// has boundary faces.
+template <typename T, int N, int MODE, bool BND>
 __global__ __launch_bounds__((Tile<N>::NT), (sizeof(T) == 4 ? EWDG_OCC32 : 2)) void k_stage(StageArgs<T> a) {
   const int nblk = static_cast<int>((a.K + Tile<N>::E - 1) / Tile<N>::E);
-  stage_body<T, N, MODE>(a, static_cast<int>(xcd_tile(blockIdx.x, nblk)));
+  stage_body<T, N, MODE, BND>(a, static_cast<int>(xcd_tile(blockIdx.x, nblk)));
 }
 
 // Many independent meshes of the same degree in one ragged launch: request r
@@ -994,6 +1012,7 @@ static StageArgs<T> stage_args(const Dev& d, const void* qin, const void* sin, v
   a.conn = d.conn;
   a.nbrnode = d.nbrnode;
   a.fmask = d.fmask;
+  a.bcm = d.bcm;
   a.K = d.K;
   a.a = static_cast<T>(c.a);
   a.b = static_cast<T>(c.b);
@@ -1017,12 +1036,23 @@ static hipError_t stage_impl(const Dev& d, int mode, const void* qin, const void
   if (mode == 2 && !rhsv) return hipErrorInvalidValue;
   const StageArgs<T> a = stage_args<T>(d, qin, sin, qout, sout, out, c, rhsv);
   const unsigned grid = static_cast<unsigned>((d.K + TL::E - 1) / TL::E);
+  if (d.bcm) {
+    // bounded meshes: the forward stage and the operator (the adjoint and the
+    // recording stage are periodic only)
+    if (mode == 0)
+      hipLaunchKernelGGL((k_stage<T, N, 0, true>), dim3(grid), dim3(TL::NT), 0, st, a);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_stage<T, N, 1, true>), dim3(grid), dim3(TL::NT), 0, st, a);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage<T, N, 0>), dim3(grid), dim3(TL::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 0, false>), dim3(grid), dim3(TL::NT), 0, st, a);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_stage<T, N, 1>), dim3(grid), dim3(TL::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 1, false>), dim3(grid), dim3(TL::NT), 0, st, a);
   else
-    hipLaunchKernelGGL((k_stage<T, N, 2>), dim3(grid), dim3(TL::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 2, false>), dim3(grid), dim3(TL::NT), 0, st, a);
   return hipGetLastError();
 }
 

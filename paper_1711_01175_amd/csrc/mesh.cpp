@@ -23,7 +23,7 @@ struct TripleHash {
 }  // namespace
 
 int build_mesh(int64_t K, const int64_t* EToV, const double* VXYZ, MeshData& m,
-               std::string& err) {
+               std::string& err, int bc) {
   if (K <= 0 || K >= (int64_t(1) << 26)) {
     err = "element count out of range";
     return EWDG_EINVAL;
@@ -133,10 +133,18 @@ int build_mesh(int64_t K, const int64_t* EToV, const double* VXYZ, MeshData& m,
       m.conn[k2 * 4 + g] = static_cast<int32_t>(k * 32 + f * 6 + p2);
       it->second = -1;
     }
+  m.bc = bc;
+  m.bcm.assign(K, 0);
   for (int64_t i = 0; i < K * 4; ++i)
     if (m.conn[i] < 0) {
-      err = "face without a partner (only periodic meshes are supported)";
-      return EWDG_EMESH;
+      if (bc == 0) {
+        err = "face without a partner (a periodic mesh was asked for)";
+        return EWDG_EMESH;
+      }
+      const int64_t k = i / 4;
+      const int f = static_cast<int>(i % 4);
+      m.conn[i] = static_cast<int32_t>(k * 32 + f * 6);   // itself, same face, identity permutation
+      m.bcm[k] |= bc << (2 * f);
     }
   return EWDG_OK;
 }

@@ -20,12 +20,19 @@ struct MeshData {
   std::vector<double> A;      // [K][9] map matrix, x = X0 + A (rhat + 1)
   std::vector<double> Ainv;   // [K][9]
   std::vector<double> inradius;  // [K] 3|K| / |dK|
+  // boundary faces (bounded meshes): bc of every face without a partner, 2
+  // bits per face (1 traction-free, 2 absorbing); such a face's conn entry
+  // points at the element itself, same face, identity vertex permutation
+  std::vector<int32_t> bcm;
+  int bc = 0;
 };
 
 // Returns 0 on success or an error code (EWDG_EMESH / EWDG_EINVAL) with a
-// message in err.
+// message in err.  bc = 0: every face must have a partner (periodic meshes);
+// 1 or 2: faces without a partner are traction-free or absorbing boundary
+// faces.
 int build_mesh(int64_t K, const int64_t* EToV, const double* VXYZ, MeshData& m,
-               std::string& err);
+               std::string& err, int bc = 0);
 
 // Owning element of a point (all barycentrics >= -tol, lowest index on
 // ties) and its reference coordinates; returns -1 if no element contains it.

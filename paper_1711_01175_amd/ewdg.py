@@ -37,11 +37,14 @@ _P_d = ctypes.POINTER(ctypes.c_double)
 _P_i = ctypes.POINTER(ctypes.c_int)
 
 # name -> argtypes (all return int unless listed in _RESTYPE)
+BC_PERIODIC, BC_FREE, BC_ABSORBING = 0, 1, 2   # boundary conditions of ewdg_set_mesh_bc
+
 SIGNATURES = {
     "ewdg_create": [_c_i, _c_i, _c_p, ctypes.POINTER(_c_p)],
     "ewdg_destroy": [_c_p],
     "ewdg_set_stream": [_c_p, _c_p],
     "ewdg_set_mesh": [_c_p, _c_i64, _c_p, _c_p],
+    "ewdg_set_mesh_bc": [_c_p, _c_i64, _c_p, _c_p, _c_i],
     "ewdg_sizes": [_c_p, _P_i, _P_i, _P_i],
     "ewdg_node_points": [_c_p, _c_p],
     "ewdg_quadrature_points": [_c_p, _c_p],
@@ -219,12 +222,18 @@ class Context:
                 t.record_stream(s)
 
     # ----------------------------------------------------------------- mesh
-    def set_mesh(self, EToV, VXYZ):
+    def set_mesh(self, EToV, VXYZ, boundary=None):
+        """boundary: None (periodic: every face has a partner), "free"
+        (traction-free) or "absorbing" for the faces without a partner."""
         EToV = _host(EToV, np.int64)
         VXYZ = _host(VXYZ, np.float64)
         K = EToV.shape[0]
         assert EToV.shape == (K, 4) and VXYZ.shape == (K, 4, 3)
-        self._check(self.lib.ewdg_set_mesh(self.h, K, _ptr(EToV), _ptr(VXYZ)), "set_mesh")
+        codes = {None: BC_PERIODIC, "free": BC_FREE, "absorbing": BC_ABSORBING}
+        if boundary not in codes:
+            raise EwdgError(EWDG_EINVAL, f"unknown boundary condition {boundary!r}")
+        bc = codes[boundary]
+        self._check(self.lib.ewdg_set_mesh_bc(self.h, K, _ptr(EToV), _ptr(VXYZ), bc), "set_mesh")
         self.K = K
 
     def node_points(self):

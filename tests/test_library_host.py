@@ -232,3 +232,27 @@ def test_transport_rejects_bad_arguments():
         T.solve()
     with pytest.raises(B.EwdgError):
         T.set_problem(np.zeros((T.E, T.Nq)), np.zeros((T.E, 4, T.Nqf)))
+
+
+def test_bounded_meshes_mark_boundary_faces():
+    """A box mesh (no periodic wrap) is refused as periodic; with a boundary
+    condition its 12 n^2 boundary faces point at their own element."""
+    from workloads.mesh import kuhn_box_mesh
+    n = 3
+    EToV, VXYZ = kuhn_box_mesh(n, shuffle_seed=2)
+    c = P.Context(2, 64)
+    with pytest.raises(B.EwdgError):
+        c.set_mesh(EToV, VXYZ)
+    for bc in ("free", "absorbing"):
+        c = P.Context(2, 64)
+        c.set_mesh(EToV, VXYZ, boundary=bc)
+        conn = c.connectivity()
+        nb = conn >> 5
+        selfref = nb == np.arange(c.K)[:, None]
+        assert selfref.sum() == 12 * n * n
+        # interior faces still point back
+        for k, f in zip(*np.nonzero(~selfref)):
+            g = (conn[k, f] & 31) // 6
+            assert conn[nb[k, f], g] >> 5 == k
+    with pytest.raises(B.EwdgError):
+        P.Context(2, 64).set_mesh(EToV, VXYZ, boundary="nonsense")
