@@ -196,14 +196,14 @@ def build_workload(n, N):
     return EToV, VXYZ, media
 
 
-def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ):
+def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, boundary=None):
     import torch
 
     import paper_1711_01175_amd as P
     from workloads import media
     stream = torch.cuda.current_stream()
     c = P.Context(N, prec, stream=stream.cuda_stream)
-    c.set_mesh(EToV, VXYZ)
+    c.set_mesh(EToV, VXYZ, boundary=boundary)
     c.bind_workspace()
     xyz = c.quadrature_points()
     rho, lam, mu = media.smooth(xyz)
@@ -500,6 +500,23 @@ def run_transport(d=3, p=4, n=48):
             "table1_d_n_p_paper_ours": counts}
 
 
+def run_bounded(n=32, N=4, steps=20, warmup=2):
+    """The headline workload on the box [-1,1]^3 without the periodic wrap:
+    stage time with traction-free and with absorbing boundary faces (12 n^2
+    of them), against the periodic stage of the same run."""
+    from workloads.mesh import kuhn_box_mesh
+    EToV, VXYZ = kuhn_box_mesh(n)
+    out = {"workload": f"{n}^3 hexes x 6 = {6 * n ** 3} tets in the box, N={N}, {12 * n * n} boundary faces, "
+                       f"smooth media, Ricker source, {steps} steps"}
+    for prec in (32, 64):
+        row = {}
+        for bc in ("free", "absorbing"):
+            r = run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, boundary=bc)
+            row[bc + "_stage_us"] = round(r["ms"] * 1e3 / (5 * steps), 2)
+        out[f"fp{prec}"] = row
+    return out
+
+
 def cpu_baseline(N, n_sample, seconds):
     """Time the FP64 oracle's RHS on a smaller mesh of the same workload
     (per-element work does not depend on the mesh size)."""
@@ -661,6 +678,8 @@ def main():
         line["implicit"] = run_implicit()
     if not args.no_transport:
         line["transport"] = run_transport()
+    if not args.no_accuracy:
+        line["bounded"] = run_bounded()
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(args.N, args.cpu_n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
