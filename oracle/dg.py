@@ -67,9 +67,12 @@ def _double_dot(e6, s6):
 class Elastic:
     """The oracle operator L(q) for one mesh, degree and material."""
 
-    def __init__(self, N, VXYZ, rho_q, lam_q, mu_q, flux="upwind", boundary=None):
+    def __init__(self, N, VXYZ, rho_q, lam_q, mu_q, flux="upwind", boundary=None, mass="exact"):
         if flux not in ("upwind", "central"):
             raise ValueError(flux)
+        if mass not in ("exact", "wadg"):
+            raise ValueError(mass)
+        self.mass = mass
         if boundary not in (None, "free", "absorbing"):
             raise ValueError(boundary)
         self.flux = flux
@@ -97,7 +100,20 @@ class Elastic:
             k1 = min(k0 + 4096, self.K)
             wr = (w[None, :] * self.rho_q[k0:k1])[:, :, None] * R.Psi_q[None, :, :]   # [k][q][n]
             self.Mrho[k0:k1] = M.J[k0:k1, None, None] * (R.Psi_q.T[None, :, :] @ wr)
-        self.Mrho_inv = np.linalg.inv(self.Mrho)
+        if mass == "exact":
+            self.Mrho_inv = np.linalg.inv(self.Mrho)
+        else:
+            # weight-adjusted approximation M_rho^-1 ~ M^-1 M_{1/rho} M^-1; with the
+            # orthonormal modes M = J I and M_{1/rho} = J Psi^T diag(w / rho) Psi,
+            # so it is J^-1 Psi^T diag(w / rho) Psi
+            self.Mrho_inv = np.empty_like(self.Mrho)
+            for k0 in range(0, self.K, 4096):
+                k1 = min(k0 + 4096, self.K)
+                wr = (w[None, :] / self.rho_q[k0:k1])[:, :, None] * R.Psi_q[None, :, :]
+                self.Mrho_inv[k0:k1] = (R.Psi_q.T[None, :, :] @ wr) / M.J[k0:k1, None, None]
+        # the velocity mass the scheme inverts (M_rho, or the inverse of its
+        # weight-adjusted approximation): the energy that the flux dissipates
+        self.Mvel = self.Mrho if mass == "exact" else np.linalg.inv(self.Mrho_inv)
         wsum = w.sum()
         self.rho_bar = self.rho_q @ w / wsum
         self.lam_bar = self.lam_q @ w / wsum
@@ -277,9 +293,10 @@ class Elastic:
         return float(ev + ee)
 
     def energy_rate(self, c, cdot):
-        """dE/dt along the direction cdot (the semi-discrete energy rate)."""
+        """dE/dt along the direction cdot (the semi-discrete energy rate), with
+        the kinetic energy in the velocity mass the scheme inverts."""
         R, M = self.ref, self.mesh
-        rv = np.einsum('kcm,kmn,kcn->', cdot[:, 0:3], self.Mrho, c[:, 0:3])
+        rv = np.einsum('kcm,kmn,kcn->', cdot[:, 0:3], self.Mvel, c[:, 0:3])
         eq = np.einsum('qm,kfm->kfq', R.Psi_q, c[:, 3:9])
         edq = np.einsum('qm,kfm->kfq', R.Psi_q, cdot[:, 3:9])
         tr = eq[:, 0] + eq[:, 1] + eq[:, 2]
