@@ -134,6 +134,21 @@ int ewdg_bind_workspace(ewdg_ctx* ctx, void* device_ptr, size_t bytes, int max_r
  * to zero at t = 0. */
 int ewdg_set_material(ewdg_ctx* ctx, const double* rho_q, const double* lam_q,
                       const double* mu_q);
+/* Mass inverse on the velocity rows (the element-local rho-weighted inverse
+ * mass of the update, cf. the weighted norms of Sec. 2).  EWDG_MASS_EXACT
+ * (default): W_rho = M_rho^-1 M from the quadrature mass with the sampled
+ * density, a stored Np x Np matrix per element.  EWDG_MASS_WEIGHT_ADJUSTED:
+ * M_rho^-1 ~ M^-1 M_{1/rho} M^-1, applied as the L2_Q projection of
+ * (velocity right-hand side) / rho at the quadrature points (the point
+ * source as M^-1 phi(x_s)): exact when rho is constant on every element,
+ * otherwise a different (energy-stable) scheme; it reads Nq values of
+ * 1/rho per element instead of Np^2.  Needs a bound workspace and a
+ * periodic mesh; batched stepping and the adjoint refuse it (EWDG_EINVAL,
+ * or EWDG_ESTATE while an adjoint workspace is bound).  The implicit step
+ * must be set up again.  ewdg_energy keeps the physical energy (exact
+ * M_rho). */
+enum { EWDG_MASS_EXACT = 0, EWDG_MASS_WEIGHT_ADJUSTED = 1 };
+int ewdg_set_mass_inverse(ewdg_ctx* ctx, int mode);
 
 /* State in the public nodal layout q[K][9][Np] of the context precision;
  * on_device selects device (1) or host (0) memory. */

@@ -170,6 +170,9 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.nbrface = reinterpret_cast<int32_t*>(take(96 * Nfp * 4));
   d.fmask = reinterpret_cast<int32_t*>(take(4 * Nfp * 4));
   d.bcm_buf = reinterpret_cast<int32_t*>(take(K * 4));
+  d.rinv = take(((Nq + 3) / 4 * 4) * K * ts);
+  d.svw = take(Np * ts);
+  d.rhsw = take(3 * Np * K * ts);
   d.bcm = (base && c->mesh.bc != 0) ? d.bcm_buf : nullptr;
   return off;
 }
@@ -290,6 +293,7 @@ int ewdg_set_mesh_bc(ewdg_ctx* c, int64_t K, const int64_t* EToV, const double* 
   c->fwd_done = false;
   c->imp_bound = false;
   c->imp_ready = false;
+  c->d.wadg = false;
   c->d.K = K;
   return EWDG_OK;
 }
@@ -517,6 +521,7 @@ int ewdg_set_material(ewdg_ctx* c, const double* rho, const double* lam, const d
   if ((rc = upload(c, c->d.lam64, lam, bytes))) return rc;
   if ((rc = upload(c, c->d.mu64, mu, bytes))) return rc;
   if ((rc = c->hip(launch_material(c->d, c->stream), "material setup"))) return rc;
+  if (c->d.wadg && (rc = c->hip(launch_rinv(c->d, c->stream), "1/rho"))) return rc;
   // zero state at t = 0
   const size_t sb = static_cast<size_t>(K) * c->re.Np * c->tsz();
   if ((rc = c->hip(hipMemsetAsync(c->d.q[0], 0, 9 * sb, c->stream), "memset"))) return rc;
@@ -531,6 +536,24 @@ int ewdg_set_material(ewdg_ctx* c, const double* rho, const double* lam, const d
     if ((rc = c->hip(launch_source_vector(c->d, c->src_elem, c->stream), "source vector"))) return rc;
   }
   return c->hip(hipStreamSynchronize(c->stream), "material sync");
+}
+
+int ewdg_set_mass_inverse(ewdg_ctx* c, int mode) {
+  if (int rc = need(c, true, true, false)) return c ? c->fail(rc, "set_mass_inverse needs a bound workspace") : rc;
+  if (mode != EWDG_MASS_EXACT && mode != EWDG_MASS_WEIGHT_ADJUSTED) return c->fail(EWDG_EINVAL, "unknown mass inverse");
+  if (mode == EWDG_MASS_WEIGHT_ADJUSTED && c->mesh.bc != 0)
+    return c->fail(EWDG_EINVAL, "the weight-adjusted mass inverse needs a periodic mesh");
+  if (c->adj_bound && mode != EWDG_MASS_EXACT)
+    return c->fail(EWDG_ESTATE, "an adjoint workspace is bound (the adjoint needs the exact mass inverse)");
+  c->d.wadg = mode == EWDG_MASS_WEIGHT_ADJUSTED;
+  c->imp_ready = false;   // the local matrices depend on it
+  c->fwd_done = false;
+  int rc;
+  if (c->d.wadg && c->has_material) {
+    if ((rc = c->hip(launch_rinv(c->d, c->stream), "1/rho"))) return rc;
+    return c->hip(hipStreamSynchronize(c->stream), "1/rho sync");
+  }
+  return EWDG_OK;
 }
 
 int ewdg_set_state(ewdg_ctx* c, const void* q, int on_device, double t) {
@@ -588,6 +611,16 @@ int ewdg_set_source(ewdg_ctx* c, const double xs[3], const double dir[3], double
   const std::vector<double> row = nodal_row(c->re, rh);
   int rc;
   if ((rc = upload(c, c->d.srcb, row.data(), row.size() * 8))) return rc;
+  {
+    // M^-1 phi(x_s) (M = J Mhat) for the weight-adjusted mass inverse
+    const int Np = c->re.Np;
+    std::vector<double> Mi(c->re.Mhat);
+    if (!invert(Np, Mi)) return c->fail(EWDG_EINVAL, "reference mass matrix is singular");
+    std::vector<double> sw(Np, 0.0);
+    for (int i = 0; i < Np; ++i)
+      for (int j = 0; j < Np; ++j) sw[i] += Mi[static_cast<size_t>(i) * Np + j] * row[j] / c->mesh.J[e];
+    if ((rc = upload_run(c, c->d.svw, sw))) return rc;
+  }
   c->has_source = true;
   c->fwd_done = false;
   c->src_elem = e;
@@ -809,7 +842,8 @@ int ewdg_step_batch(ewdg_ctx* const* ctxs, int n, const double* dts, int nsteps,
   if (table_bytes < need_b) return EWDG_ENOMEM;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < n; ++i)
-    if (ctxs[i] && ctxs[i]->mesh.bc != 0) return ctxs[i]->fail(EWDG_EINVAL, "batched stepping needs periodic meshes");
+    if (ctxs[i] && (ctxs[i]->mesh.bc != 0 || ctxs[i]->d.wadg))
+      return ctxs[i]->fail(EWDG_EINVAL, "batched stepping needs periodic meshes and the exact mass inverse");
   for (int i = 0; i < n; ++i) {
     ewdg_ctx* c = ctxs[i];
     if (!c) return EWDG_EINVAL;
@@ -999,7 +1033,8 @@ int ewdg_step_batch_static(ewdg_ctx* const* ctxs, int n, const double* dts, int 
   if (need_b > kStaticTableBytes)
     return ctxs[0]->fail(EWDG_ENOMEM, "batch too large for the static launch table (ewdg_static_table_max_bytes)");
   for (int i = 0; i < n; ++i)
-    if (ctxs[i] && ctxs[i]->mesh.bc != 0) return ctxs[i]->fail(EWDG_EINVAL, "batched stepping needs periodic meshes");
+    if (ctxs[i] && (ctxs[i]->mesh.bc != 0 || ctxs[i]->d.wadg))
+      return ctxs[i]->fail(EWDG_EINVAL, "batched stepping needs periodic meshes and the exact mass inverse");
   for (int i = 0; i < n; ++i) {
     ewdg_ctx* c = ctxs[i];
     if (!c) return EWDG_EINVAL;
@@ -1165,7 +1200,8 @@ int ewdg_adjoint_workspace_bytes_overlapped(const ewdg_ctx* c, int max_steps, in
 
 int ewdg_bind_adjoint_workspace(ewdg_ctx* c, void* ptr, size_t bytes, int max_steps, int checkpoint_every) {
   if (int rc = need(c, true, true, false)) return c ? c->fail(rc, "bind the forward workspace first") : rc;
-  if (c->mesh.bc != 0) return c->fail(EWDG_EINVAL, "the adjoint needs a periodic mesh");
+  if (c->mesh.bc != 0 || c->d.wadg)
+    return c->fail(EWDG_EINVAL, "the adjoint needs a periodic mesh and the exact mass inverse");
   if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
     return c->fail(EWDG_EINVAL, "adjoint workspace must be a non-null 256-byte aligned device pointer");
   if (max_steps < 1 || checkpoint_every < 1) return c->fail(EWDG_EINVAL, "max_steps and checkpoint_every must be >= 1");

@@ -63,6 +63,12 @@ struct Dev {
   int32_t* fmask = nullptr;          // [4][Nfp]
   int32_t* bcm = nullptr;            // [K] boundary codes, 2 bits per face; null for periodic meshes
   int32_t* bcm_buf = nullptr;        // its storage in the workspace
+  // weight-adjusted mass inverse (in place of W): 1/rho at the quadrature
+  // points, the source's M^-1 phi(x_s), the raw velocity right-hand side
+  bool wadg = false;
+  void* rinv = nullptr;              // run precision [K][NqP]
+  void* svw = nullptr;               // run precision [Np]
+  void* rhsw = nullptr;              // run precision [K][3][Np]
   // scratch for setup (aliases q[1], s[1], res while no state exists)
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -87,6 +93,7 @@ hipError_t launch_project(const Dev& d, const double* fq, void* q, hipStream_t s
 hipError_t launch_evalq(const Dev& d, const void* q, double* fq, hipStream_t st);
 hipError_t launch_receivers(const Dev& d, const void* q, int nr, int step, hipStream_t st);
 hipError_t launch_energy(const Dev& d, const void* q, double* out, hipStream_t st);
+hipError_t launch_rinv(const Dev& d, hipStream_t st);   // d.rinv = 1 / rho (weight-adjusted inverse)
 bool supported_degree(int N);
 
 // Batched stages over many meshes of one degree and precision: a device

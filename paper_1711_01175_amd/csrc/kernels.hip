@@ -4,6 +4,8 @@
 // FP64 diagnostics (projection, evaluation, receivers, energy).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dev.hpp"
 #include "kcommon.hpp"
 #include "tiles.hpp"
@@ -83,7 +85,7 @@ struct FacePt {
   T sm[6], vp[3], sp[6], zp, zs;
 };
 
-template <typename T, int N, int MODE, bool BND = false>
+template <typename T, int N, int MODE, bool BND = false, bool WADG = false>
 __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   using TL = Tile<N>;
   using M = Mfma<T>;
@@ -505,13 +507,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     const int ge = e0 + e;
     if (x >= E * Np || ge >= Ke) return;
     const int64_t base = static_cast<int64_t>(ge) * 9 * Np + i;
-    if (ge == a.src_elem) {
+    if (!WADG && ge == a.src_elem) {
       const T sv = a.srcval * a.svec[i];
       o[0] += sv * a.dir0;
       o[1] += sv * a.dir1;
       o[2] += sv * a.dir2;
     }
-    if (MODE == 2) {
+    if (MODE == 2 || WADG) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.rhsv[static_cast<int64_t>(ge) * 3 * Np + c * Np + i] = o[c];
     }
@@ -519,6 +521,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     for (int m = 0; m < 6; ++m) o[3 + m] = Ser[i * SE + m * 16 + e];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
+      if (WADG && c < 3) continue;   // the velocity rows are k_wadg's
       if (MODE == 0) {
         a.out[base + c * Np] = o[c];
       } else {
@@ -544,19 +547,27 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
     T rv[9], qv[NQV];
     if constexpr (MODE != 0) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) rv[c] = a.out[base + c * Np];
+      for (int c = 0; c < 9; ++c) rv[c] = (WADG && c < 3) ? T(0) : a.out[base + c * Np];
 #pragma unroll
-      for (int c = 0; c < NQV; ++c) qv[c] = a.qin[base + (c + 9 - NQV) * Np];
+      for (int c = 0; c < NQV; ++c) qv[c] = (WADG && c + 9 - NQV < 3) ? T(0) : a.qin[base + (c + 9 - NQV) * Np];
     }
-    const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
     T o[9] = {0, 0, 0};
+    if constexpr (WADG) {
+      // weight-adjusted mass inverse: the raw velocity right-hand side goes
+      // to k_wadg, no W_rho stream
+      o[0] = Srv[i * SV + e];
+      o[1] = Srv[i * SV + 16 + e];
+      o[2] = Srv[i * SV + 32 + e];
+    } else {
+      const T* Wm = a.W + static_cast<int64_t>(ge) * Np * Np + i;
 #pragma unroll
-    for (int j0 = 0; j0 < Np; j0 += CW) {
-      constexpr int n0 = CW;
-      T w[n0];
+      for (int j0 = 0; j0 < Np; j0 += CW) {
+        constexpr int n0 = CW;
+        T w[n0];
 #pragma unroll
-      for (int u = 0; u < n0; ++u) w[u] = (j0 + u < Np) ? Wm[(j0 + u) * Np] : T(0);
-      wdot(p, w, j0, (Np - j0) < CW ? (Np - j0) : CW, o);
+        for (int u = 0; u < n0; ++u) w[u] = (j0 + u < Np) ? Wm[(j0 + u) * Np] : T(0);
+        wdot(p, w, j0, (Np - j0) < CW ? (Np - j0) : CW, o);
+      }
     }
     upd_finish(p, o, rv, qv);
   }
@@ -719,11 +730,128 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 }
 
 // One mesh: workgroups map to element tiles, XCD-contiguous.  BND: the mesh
-// has boundary faces.
-template <typename T, int N, int MODE, bool BND>
+// has boundary faces.  WADG: the weight-adjusted mass inverse (k_wadg
+// applies it and updates the velocity).
+template <typename T, int N, int MODE, bool BND, bool WADG>
 __global__ __launch_bounds__((Tile<N>::NT), (sizeof(T) == 4 ? EWDG_OCC32 : 2)) void k_stage(StageArgs<T> a) {
   const int nblk = static_cast<int>((a.K + Tile<N>::E - 1) / Tile<N>::E);
-  stage_body<T, N, MODE, BND>(a, static_cast<int>(xcd_tile(blockIdx.x, nblk)));
+  stage_body<T, N, MODE, BND, WADG>(a, static_cast<int>(xcd_tile(blockIdx.x, nblk)));
+}
+
+template <typename T>
+struct WadgArgs {
+  const T* r;          // [K][3][Np] raw velocity right-hand side
+  const T* rinv;       // [K][NqP] 1 / rho at the quadrature points
+  const T* svw;        // [Np] M^-1 phi(x_s) of the source element
+  const T* Vqpad;
+  const T* Pqpad;
+  T* out;              // mode 0: operator output [K][9][Np]; mode 1: LSRK register
+  const T* qin;
+  T* qout;
+  int64_t K;
+  T a, b, dt, srcval, dir0, dir1, dir2;
+  int64_t src_elem;
+};
+
+// Weight-adjusted velocity update (the alternative to W_rho = M_rho^-1 M):
+// u = P_Q diag(1/rho) V_Q r with r the velocity right-hand side plus the
+// point source M^-1 phi(x_s) f, i.e. M^-1 M_{1/rho} M^-1 applied to the weak
+// residual; then u into the velocity rows of the operator output (mode 0) or
+// the LSRK update of the velocity (mode 1).  16 elements per workgroup, V_Q
+// in chunks of 64 quadrature rows into LDS (scaled by 1/rho), P_Q
+// accumulated across the chunks on the matrix cores.
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((Tile<N>::NT)) void k_wadg(WadgArgs<T> a) {
+  using TL = Tile<N>;
+  using M = Mfma<T>;
+  using acc_t = typename M::acc_t;
+  constexpr int Np = TL::Np, Nq = TL::Nq, NqP = TL::NqP, E = TL::E, NpK = TL::NpK, NqK = TL::NqK;
+  constexpr int RT = TL::RT, QT = TL::QT, NT = TL::NT, KD = NpK / 4;
+  constexpr int QCW = 64, NQC = (QT * 16 + QCW - 1) / QCW, SR = 48;
+  __shared__ T Sr[NpK * SR];
+  __shared__ T Sz[QCW * SR];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lg = l >> 4;
+  const int Ke = static_cast<int>(a.K);
+  const int e0 = blockIdx.x * E;
+  for (int x = tid; x < E * 3 * Np; x += NT) {
+    const int e = x / (3 * Np), rem = x % (3 * Np), c = rem / Np, j = rem % Np;
+    T v = T(0);
+    if (e0 + e < Ke) {
+      v = a.r[static_cast<int64_t>(e0 + e) * 3 * Np + rem];
+      if (e0 + e == a.src_elem) v += a.srcval * (c == 0 ? a.dir0 : (c == 1 ? a.dir1 : a.dir2)) * a.svw[j];
+    }
+    Sr[j * SR + c * 16 + e] = v;
+  }
+  for (int x = tid; x < (NpK - Np) * SR; x += NT) Sr[Np * SR + x] = T(0);
+  __syncthreads();
+  acc_t u[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
+  for (int qc = 0; qc < NQC; ++qc) {
+    const int q0 = qc * QCW;
+    const int Rq = q0 / 16 + w;
+    if (w < QCW / 16 && Rq < QT) {
+      acc_t z[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) z[c] = acc_t{0, 0, 0, 0};
+      const T* Vr = a.Vqpad + (Rq * KD) * 64 + l;
+#pragma unroll
+      for (int kk = 0; kk < KD; ++kk) {
+        const T vf = Vr[kk * 64];
+        const int row = (4 * kk + lg) * SR + lr;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) z[c] = M::mma(vf, Sr[row + c * 16], z[c]);
+      }
+      const int ge = e0 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = Rq * 16 + M::row(lg, r);
+        const T ri = (q < Nq && ge < Ke) ? a.rinv[static_cast<int64_t>(ge) * NqP + q] : T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Sz[(q - q0) * SR + c * 16 + lr] = z[c][r] * ri;
+      }
+    }
+    __syncthreads();
+    if (w < RT) {
+      const int rows = (NqK - q0) < QCW ? (NqK - q0) : QCW;
+      const T* Pr = a.Pqpad + (w * (NqK / 4) + q0 / 4) * 64 + l;
+#pragma unroll
+      for (int kq = 0; kq < QCW / 4; ++kq) {
+        if (4 * kq < rows) {
+          const T pf = Pr[kq * 64];
+          const int row = (4 * kq + lg) * SR + lr;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) u[c] = M::mma(pf, Sz[row + c * 16], u[c]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (w < RT) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = w * 16 + M::row(lg, r);
+      if (i < Np) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Sr[i * SR + c * 16 + lr] = u[c][r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < E * 3 * Np; x += NT) {
+    const int e = x / (3 * Np), rem = x % (3 * Np), c = rem / Np, i = rem % Np;
+    if (e0 + e >= Ke) continue;
+    const T uv = Sr[i * SR + c * 16 + e];
+    const int64_t base = static_cast<int64_t>(e0 + e) * 9 * Np + rem;
+    if (MODE == 0) {
+      a.out[base] = uv;
+    } else {
+      const T rr = a.a * a.out[base] + a.dt * uv;
+      a.out[base] = rr;
+      a.qout[base] = a.qin[base] + a.b * rr;
+    }
+  }
 }
 
 // Many independent meshes of the same degree in one ragged launch: request r
@@ -1036,23 +1164,59 @@ static hipError_t stage_impl(const Dev& d, int mode, const void* qin, const void
   if (mode == 2 && !rhsv) return hipErrorInvalidValue;
   const StageArgs<T> a = stage_args<T>(d, qin, sin, qout, sout, out, c, rhsv);
   const unsigned grid = static_cast<unsigned>((d.K + TL::E - 1) / TL::E);
+  if (d.wadg) {
+    // weight-adjusted mass inverse (periodic meshes): the stage without the
+    // velocity update, then k_wadg
+    if (d.bcm || mode == 2 || !d.rhsw) return hipErrorInvalidValue;
+    StageArgs<T> aw = a;
+    aw.rhsv = static_cast<T*>(d.rhsw);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_stage<T, N, 0, false, true>), dim3(grid), dim3(TL::NT), 0, st, aw);
+    else
+      hipLaunchKernelGGL((k_stage<T, N, 1, false, true>), dim3(grid), dim3(TL::NT), 0, st, aw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    WadgArgs<T> w;
+    w.r = static_cast<const T*>(d.rhsw);
+    w.rinv = static_cast<const T*>(d.rinv);
+    w.svw = static_cast<const T*>(d.svw);
+    w.Vqpad = static_cast<const T*>(d.Vqpad);
+    w.Pqpad = static_cast<const T*>(d.Pqpad);
+    w.out = static_cast<T*>(out);
+    w.qin = static_cast<const T*>(qin);
+    w.qout = static_cast<T*>(qout);
+    w.K = d.K;
+    w.a = a.a;
+    w.b = a.b;
+    w.dt = a.dt;
+    w.srcval = a.srcval;
+    w.dir0 = a.dir0;
+    w.dir1 = a.dir1;
+    w.dir2 = a.dir2;
+    w.src_elem = a.src_elem;
+    if (mode == 0)
+      hipLaunchKernelGGL((k_wadg<T, N, 0>), dim3(grid), dim3(TL::NT), 0, st, w);
+    else
+      hipLaunchKernelGGL((k_wadg<T, N, 1>), dim3(grid), dim3(TL::NT), 0, st, w);
+    return hipGetLastError();
+  }
   if (d.bcm) {
     // bounded meshes: the forward stage and the operator (the adjoint and the
     // recording stage are periodic only)
     if (mode == 0)
-      hipLaunchKernelGGL((k_stage<T, N, 0, true>), dim3(grid), dim3(TL::NT), 0, st, a);
+      hipLaunchKernelGGL((k_stage<T, N, 0, true, false>), dim3(grid), dim3(TL::NT), 0, st, a);
     else if (mode == 1)
-      hipLaunchKernelGGL((k_stage<T, N, 1, true>), dim3(grid), dim3(TL::NT), 0, st, a);
+      hipLaunchKernelGGL((k_stage<T, N, 1, true, false>), dim3(grid), dim3(TL::NT), 0, st, a);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage<T, N, 0, false>), dim3(grid), dim3(TL::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 0, false, false>), dim3(grid), dim3(TL::NT), 0, st, a);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_stage<T, N, 1, false>), dim3(grid), dim3(TL::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 1, false, false>), dim3(grid), dim3(TL::NT), 0, st, a);
   else
-    hipLaunchKernelGGL((k_stage<T, N, 2, false>), dim3(grid), dim3(TL::NT), 0, st, a);
+    hipLaunchKernelGGL((k_stage<T, N, 2, false, false>), dim3(grid), dim3(TL::NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1108,6 +1272,30 @@ hipError_t launch_source_vector(const Dev& d, int64_t elem, hipStream_t st) {
   }
   EWDG_DISPATCH(d.N, hipLaunchKernelGGL((k_source_vector<double, NN>), dim3(1), dim3(256), 0, st, d, elem);
                 return hipGetLastError());
+}
+
+// 1 / rho at the quadrature points in the run precision, padded rows zero.
+template <typename T>
+__global__ void k_rinv(const double* __restrict__ rho, T* __restrict__ rinv, int64_t K, int Nq, int NqP) {
+  const int64_t n = K * NqP;
+  for (int64_t x = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; x < n;
+       x += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t k = x / NqP;
+    const int q = static_cast<int>(x - k * NqP);
+    rinv[x] = q < Nq ? static_cast<T>(1.0 / rho[k * Nq + q]) : T(0);
+  }
+}
+
+hipError_t launch_rinv(const Dev& d, hipStream_t st) {
+  const int NqP = (d.Nq + 3) / 4 * 4;
+  const int64_t n = d.K * NqP;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 65536));
+  if (d.prec == 32)
+    hipLaunchKernelGGL(k_rinv<float>, dim3(g), dim3(256), 0, st, d.rho64, static_cast<float*>(d.rinv), d.K, d.Nq, NqP);
+  else
+    hipLaunchKernelGGL(k_rinv<double>, dim3(g), dim3(256), 0, st, d.rho64, static_cast<double*>(d.rinv), d.K, d.Nq,
+                       NqP);
+  return hipGetLastError();
 }
 
 hipError_t launch_sigma(const Dev& d, const void* q, void* s, hipStream_t st) {

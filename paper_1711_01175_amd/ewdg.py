@@ -53,6 +53,7 @@ SIGNATURES = {
     "ewdg_workspace_bytes": [_c_p, _c_i, _c_i, ctypes.POINTER(_c_sz)],
     "ewdg_bind_workspace": [_c_p, _c_p, _c_sz, _c_i, _c_i],
     "ewdg_set_material": [_c_p, _c_p, _c_p, _c_p],
+    "ewdg_set_mass_inverse": [_c_p, _c_i],
     "ewdg_set_state": [_c_p, _c_p, _c_i, _c_d],
     "ewdg_get_state": [_c_p, _c_p, _c_i, _P_d],
     "ewdg_project_quadrature": [_c_p, _c_p, _c_p],
@@ -285,6 +286,14 @@ class Context:
         self._check(self.lib.ewdg_set_material(self.h, _ptr(r), _ptr(l), _ptr(m)), "set_material")
 
     # ---------------------------------------------------------------- state
+    def set_mass_inverse(self, mode):
+        """"exact" (W_rho = M_rho^-1 M, the default) or "weight-adjusted"
+        (M^-1 M_{1/rho} M^-1)."""
+        codes = {"exact": 0, "weight-adjusted": 1}
+        if mode not in codes:
+            raise EwdgError(EWDG_EINVAL, f"unknown mass inverse {mode!r}")
+        self._check(self.lib.ewdg_set_mass_inverse(self.h, codes[mode]), "set_mass_inverse")
+
     def set_state(self, q, t=0.0):
         torch = _torch()
         if isinstance(q, np.ndarray):
