@@ -196,7 +196,7 @@ def build_workload(n, N):
     return EToV, VXYZ, media
 
 
-def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, boundary=None):
+def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, boundary=None, mass="exact", keep=False):
     import torch
 
     import paper_1711_01175_amd as P
@@ -205,6 +205,7 @@ def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, boundary=None):
     c = P.Context(N, prec, stream=stream.cuda_stream)
     c.set_mesh(EToV, VXYZ, boundary=boundary)
     c.bind_workspace()
+    c.set_mass_inverse(mass)
     xyz = c.quadrature_points()
     rho, lam, mu = media.smooth(xyz)
     del xyz
@@ -223,6 +224,9 @@ def run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, boundary=None):
     ms = ev0.elapsed_time(ev1)
     energy = c.energy()
     out = dict(K=c.K, Np=c.Np, Nq=c.Nq, dt=dt, ms=ms, energy=energy, t=c.time())
+    if keep:
+        out["fq"] = c.eval_quadrature()
+        out["wq"] = c.reference_operator(8)
     c.close()
     torch.cuda.empty_cache()
     return out
@@ -517,6 +521,43 @@ def run_bounded(n=32, N=4, steps=20, warmup=2):
     return out
 
 
+def wadg_bytes_per_element(Np, Nq, b):
+    """Compulsory HBM bytes per element of a stage with the weight-adjusted
+    mass inverse: q and the LSRK register read and written (36 Np b), 1/rho,
+    lambda, mu at the quadrature points (3 Nq b), geometry and connectivity
+    (26 b + 48 B), the raw velocity right-hand side written and read (6 Np b)."""
+    return 36 * Np * b + 3 * Nq * b + 26 * b + 48 + 6 * Np * b
+
+
+def run_wadg(steps=40, warmup=2):
+    """Stage time with the weight-adjusted mass inverse (no stored W_rho) at
+    N = 4 on 32^3 x 6 tets and N = 7 on 16^3 x 6, both precisions, against
+    the exact inverse, and the two schemes' relative L2 distance after
+    warmup + steps steps (the approximation, not rounding)."""
+    out = {}
+    for N, n in ((4, 32), (7, 16)):
+        EToV, VXYZ, _ = build_workload(n, N)
+        J = _jacobians(VXYZ)
+        row = {}
+        for prec in (32, 64):
+            ex = run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, keep=True)
+            wa = run_gpu(prec, N, n, steps, warmup, EToV, VXYZ, mass="weight-adjusted", keep=True)
+            K, Np, Nq = wa["K"], wa["Np"], wa["Nq"]
+            st = wa["ms"] * 1e-3 / (5 * steps)
+            bw = wadg_bytes_per_element(Np, Nq, prec // 8) * K
+            row[f"fp{prec}"] = {"exact_stage_us": round(ex["ms"] * 1e3 / (5 * steps), 1),
+                                "wadg_stage_us": round(st * 1e6, 1),
+                                "wadg_GDOF_per_s": round(K * Np * 9 / st / 1e9, 2),
+                                "wadg_bytes_per_stage": bw,
+                                "wadg_hbm_frac": round(bw / st / 1e9 / PEAK_HBM_GBS, 3),
+                                "rel_l2_wadg_vs_exact": _l2q(wa["fq"] - ex["fq"], J, wa["wq"]) / _l2q(ex["fq"], J, wa["wq"])}
+            del ex, wa
+            print(f"wadg leg N={N} FP{prec}: {row[f'fp{prec}']}", file=sys.stderr, flush=True)
+        out[f"N{N}"] = dict(workload=f"{n}^3 hexes x 6 = {6 * n ** 3} tets, N={N}, smooth media, Ricker source, "
+                                     f"{warmup} + {steps} steps", **row)
+    return out
+
+
 def cpu_baseline(N, n_sample, seconds):
     """Time the FP64 oracle's RHS on a smaller mesh of the same workload
     (per-element work does not depend on the mesh size)."""
@@ -567,6 +608,8 @@ def main():
                     help="skip the 1000-step FP32/FP64 and oracle comparisons and the N=7 leg")
     ap.add_argument("--no-implicit", action="store_true", help="skip the locally implicit (iHDG-II) leg")
     ap.add_argument("--no-transport", action="store_true", help="skip the steady transport (iHDG-II) leg")
+    ap.add_argument("--wadg-only", action="store_true",
+                    help="run only the weight-adjusted mass inverse leg and print its JSON (for profiling)")
     ap.add_argument("--transport-only", action="store_true",
                     help="run only the steady transport leg and print its JSON (for profiling)")
     ap.add_argument("--implicit-only", action="store_true",
@@ -602,6 +645,9 @@ def main():
         return
     if args.transport_only:
         print(json.dumps({"transport": run_transport()}), flush=True)
+        return
+    if args.wadg_only:
+        print(json.dumps({"weight_adjusted": run_wadg()}), flush=True)
         return
     EToV, VXYZ, _ = build_workload(args.n, args.N)
     r32 = run_gpu(32, args.N, args.n, args.steps, args.warmup, EToV, VXYZ)
@@ -680,6 +726,7 @@ def main():
         line["transport"] = run_transport()
     if not args.no_accuracy:
         line["bounded"] = run_bounded()
+        line["weight_adjusted"] = run_wadg()
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(args.N, args.cpu_n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
