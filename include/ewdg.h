@@ -370,7 +370,11 @@ int ewdg_implicit_dt(const ewdg_ctx* ctx, double* dt, double* theta);
  * domain, the exact solution's by the volume-point rule), or max_iters.
  * iters (host) receives k; history (host, max_iters + 1 values, may be NULL)
  * the norm after every iteration, starting with ||u^0 - u^e|| (0 without
- * ue).  One synchronisation per iteration.
+ * ue).  The stopping rule is evaluated on the GPU after every sweep;
+ * iterations are queued in batches of 1, 2, 4, ... 32 with one
+ * synchronisation per batch, and those queued after the stop do nothing.
+ * EWDG_EINVAL (message "non-finite iterate") if a norm is not finite; the
+ * history then ends with it.
  * ewdg_transport_values: the last iterate at the volume points, host
  * [E][Nq] FP64. */
 typedef struct ewdg_tr ewdg_tr;

@@ -197,6 +197,7 @@ size_t tr_layout(ewdg_tr* T, char* base) {
   t.rest = reinterpret_cast<double*>(take(2 * E * 8));
   t.epart = reinterpret_cast<double*>(take(static_cast<size_t>(tr_sweep_blocks(t)) * 8));
   t.scal = reinterpret_cast<double*>(take(8 * 8));
+  t.ctl = reinterpret_cast<TrCtl*>(take(sizeof(TrCtl)));
   return off;
 }
 
@@ -367,23 +368,43 @@ int ewdg_transport_solve(ewdg_tr* T, double tol, int max_iters, int* iters, doub
   int rc;
   T->cur = 0;
   if ((rc = T->hip(launch_tr_zero(t, 0, T->stream), "zero"))) return rc;
-  double prev = T->has_exact ? std::sqrt(T->exact_norm2) : 0.0;   // ||u^0 - u^e|| with u^0 = 0
-  if (history) history[0] = prev;
-  int k = 0;
-  for (k = 1; k <= max_iters; ++k) {
-    if ((rc = T->hip(launch_tr_sweep(t, T->cur, T->has_exact, 0, T->stream), "sweep"))) return rc;
-    double s = 0.0;
-    if ((rc = T->hip(hipMemcpyAsync(&s, t.scal, 8, hipMemcpyDeviceToHost, T->stream), "norm copy"))) return rc;
+  // iterations are queued in batches (1, 2, 4, ... up to half the norm ring)
+  // and the stopping state is read once per batch; the device skips the
+  // iterations queued after the stop
+  TrCtl h;
+  h.exact = T->has_exact ? 1 : 0;
+  h.prev = T->has_exact ? std::sqrt(T->exact_norm2) : 0.0;   // ||u^0 - u^e|| with u^0 = 0
+  h.rest = T->rest_total;
+  h.tol = tol;
+  if ((rc = T->hip(hipMemcpyAsync(t.ctl, &h, sizeof(TrCtl), hipMemcpyHostToDevice, T->stream), "control upload")))
+    return rc;
+  if (history) history[0] = h.prev;
+  TrCtl r;
+  int64_t k = 1, kend = max_iters;
+  while (k <= max_iters) {
+    const int64_t batch = std::min<int64_t>({k, kTrHist / 2, static_cast<int64_t>(max_iters) - k + 1});
+    for (int64_t i = 0; i < batch; ++i)
+      if ((rc = T->hip(launch_tr_iterate(t, static_cast<int>((k + i - 1) & 1), T->has_exact, k + i, T->stream),
+                       "sweep")))
+        return rc;
+    if ((rc = T->hip(hipMemcpyAsync(&r, t.ctl, sizeof(TrCtl), hipMemcpyDeviceToHost, T->stream), "norm copy")))
+      return rc;
     if ((rc = T->hip(hipStreamSynchronize(T->stream), "norm sync"))) return rc;
-    T->cur = 1 - T->cur;
-    const double v = T->has_exact ? std::sqrt(std::max(s + T->rest_total, 0.0)) : std::sqrt(std::max(s, 0.0));
-    if (history) history[k] = v;
-    if (!std::isfinite(v)) return T->fail(EWDG_EINVAL, "non-finite iterate");
-    const bool done = T->has_exact ? std::fabs(v - prev) < tol : v < tol;
-    prev = v;
-    if (done) break;
+    const int64_t last = r.done ? r.done : k + batch - 1;
+    if (history)
+      for (int64_t j = k; j <= last; ++j) history[j] = r.hist[j % kTrHist];
+    if (r.bad) {
+      T->cur = static_cast<int>(last & 1);
+      return T->fail(EWDG_EINVAL, "non-finite iterate");
+    }
+    if (r.done) {
+      kend = r.done;
+      break;
+    }
+    k += batch;
   }
-  if (iters) *iters = k > max_iters ? max_iters : k;
+  T->cur = static_cast<int>(kend & 1);
+  if (iters) *iters = static_cast<int>(kend);
   return EWDG_OK;
 }
 

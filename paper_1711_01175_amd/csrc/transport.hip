@@ -109,6 +109,7 @@ __global__ __launch_bounds__((TrSz<D, P>::NT)) void k_tr_sweep(TrDev t, int src,
   const T* Gt = static_cast<const T*>(t.Gt);
   const int tid = threadIdx.x;
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * EPB;
+  if (t.ctl->done) return;   // the solve has stopped: a queued iteration does nothing
   // the upwind neighbours' coefficients (zero across the boundary: the
   // boundary inflow is part of c)
   for (int x = tid; x < EPB * D * Np; x += NT) {
@@ -153,15 +154,16 @@ __global__ __launch_bounds__((TrSz<D, P>::NT)) void k_tr_sweep(TrDev t, int src,
 }
 
 // The same sweep on the matrix cores (Np > 16): a workgroup takes EC = 16 CT
-// elements as matrix columns; U_new = C + sum_a G_a V_a with V_a the upwind
-// neighbours' coefficients (16x16x4 tiles: rows = output modes, k = input
-// modes, zero padded to 16 / 4).  The 4 waves own the row tiles round-robin;
-// each G_a fragment (one coalesced 64-lane load from L2) feeds CT products.
-// V_a sits in LDS in B-fragment order, so a fragment read is 64 consecutive
-// values; the result leaves through LDS in element-major rows.
+// elements as matrix columns (64 in FP32, 32 in FP64); U_new = C + sum_a G_a
+// V_a with V_a the upwind neighbours' coefficients (16x16x4 tiles: rows =
+// output modes, k = input modes, zero padded to 16 / 4).  The 4 waves own the
+// row tiles round-robin; each G_a fragment (one coalesced 64-lane load from
+// L2) feeds CT products.  The axes are taken one at a time: V_a is staged in
+// LDS in B-fragment order (a fragment read is 64 consecutive values), then
+// multiplied; the result leaves through LDS in element-major rows.
 template <typename T>
 struct TrMmaShape {
-  static constexpr int CT = sizeof(T) == 4 ? 2 : 1;   // column tiles
+  static constexpr int CT = sizeof(T) == 4 ? 4 : 2;   // column tiles
   static constexpr int EC = 16 * CT;                  // elements per workgroup
 };
 
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void k_tr_sweep_mma(TrDev t, int src, int to_e
   using acc_t = typename M::acc_t;
   constexpr int Np = S::Np, CT = TrMmaShape<T>::CT, EC = TrMmaShape<T>::EC;
   constexpr int RT = (Np + 15) / 16, KS = (Np + 3) / 4, NpR = 16 * RT;
-  constexpr int VSZ = D * KS * CT * 64;        // B-fragment ordered neighbour values
+  constexpr int VSZ = KS * CT * 64;            // one axis, B-fragment ordered
   constexpr int OSZ = EC * NpR;                // element-major result rows
   __shared__ T V[VSZ > OSZ ? VSZ : OSZ];
   __shared__ double red[4];
@@ -182,44 +184,76 @@ __global__ __launch_bounds__(256) void k_tr_sweep_mma(TrDev t, int src, int to_e
   const T* G = static_cast<const T*>(t.Gfrag);
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * EC;
-  // gather: value j of element column col along axis a -> fragment slot
-  for (int x = tid; x < D * EC * 4 * KS; x += 256) {
-    const int j = x % (4 * KS), rest = x / (4 * KS), col = rest % EC, a = rest / EC;
+  if (t.ctl->done) return;   // the solve has stopped: a queued iteration does nothing
+  static_assert(D * EC <= 256, "one thread per neighbour offset");
+  __shared__ int64_t nbe[D][EC];   // upwind neighbour of each column, -1 at the inflow boundary
+  if (tid < D * EC) {
+    const int a = tid / EC, col = tid % EC;
     const int64_t e = e0 + col;
-    T v = T(0);
-    if (j < Np && e < t.E) {
+    int64_t r = -1;
+    if (e < t.E) {
       int64_t stride = 1;
       for (int b = 0; b < a; ++b) stride *= t.n;
       const int64_t ia = (e / stride) % t.n;
       const int64_t nb = t.in_side[a] ? ia + 1 : ia - 1;
-      if (nb >= 0 && nb < t.n) v = uo[(e + (nb - ia) * stride) * Np + j];
+      if (nb >= 0 && nb < t.n) r = e + (nb - ia) * stride;
     }
-    V[(((a * KS + j / 4) * CT + col / 16) * 4 + j % 4) * 16 + col % 16] = v;
+    nbe[a][col] = r;
   }
-  __syncthreads();
   acc_t acc[(RT + 3) / 4][CT];
 #pragma unroll
   for (int rr = 0; rr < (RT + 3) / 4; ++rr)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rr][ct] = acc_t{0, 0, 0, 0};
+  __syncthreads();
+  // one axis at a time: the upwind neighbours' coefficients go to LDS, value
+  // j of column col to fragment kk = j / 4, row j % 4, and within the row to
+  // position (col + kk) mod 16 (a skew that spreads the stores, consecutive j,
+  // over the banks); then the products.  The next axis's values are loaded
+  // into registers before the current axis's products, so their latency
+  // hides behind the matrix work.
+  constexpr int RR = (RT + 3) / 4, TOT = EC * 4 * KS, NI = (TOT + 255) / 256;
+  T vr[NI];
+  auto gather = [&](int a) {
 #pragma unroll
-  for (int rr = 0; rr < (RT + 3) / 4; ++rr) {
-    const int R = w + 4 * rr;
-    if (R < RT) {
+    for (int i = 0; i < NI; ++i) {
+      const int x = tid + 256 * i;
+      if (TOT % 256 == 0 || x < TOT) {
+        const int j = x % (4 * KS), col = x / (4 * KS);
+        const int64_t s = nbe[a][col];
+        vr[i] = (j < Np && s >= 0) ? uo[s * Np + j] : T(0);
+      }
+    }
+  };
+  gather(0);
+#pragma unroll 1
+  for (int a = 0; a < D; ++a) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
+    for (int i = 0; i < NI; ++i) {
+      const int x = tid + 256 * i;
+      if (TOT % 256 == 0 || x < TOT) {
+        const int j = x % (4 * KS), col = x / (4 * KS), kk = j / 4;
+        V[((kk * CT + col / 16) * 4 + j % 4) * 16 + ((col + kk) & 15)] = vr[i];
+      }
+    }
+    __syncthreads();
+    if (a + 1 < D) gather(a + 1);
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr) {
+      const int R = w + 4 * rr;
+      if (R < RT) {
         const T* g = G + (static_cast<int64_t>(a * RT + R) * KS) * 64 + l;
-        const T* vb = V + a * KS * CT * 64 + l;
 #pragma unroll 8
         for (int kk = 0; kk < KS; ++kk) {
           const T av = g[kk * 64];
+          const T* vb = V + kk * CT * 64 + (l & 48) + ((l + kk) & 15);
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) acc[rr][ct] = M::mma(av, vb[(kk * CT + ct) * 64], acc[rr][ct]);
+          for (int ct = 0; ct < CT; ++ct) acc[rr][ct] = M::mma(av, vb[ct * 64], acc[rr][ct]);
         }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   // result rows to LDS: element col, mode i
   const int lg = l / 16;
 #pragma unroll
@@ -264,6 +298,35 @@ __global__ __launch_bounds__(1024) void k_tr_sum(const double* __restrict__ x, i
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// The stopping rule of iteration k (Sec. 6.1): sum the sweep's per-workgroup
+// parts, record the norm and set done once the rule holds (or the norm is not
+// finite).  Nothing happens once done is set.
+__global__ __launch_bounds__(1024) void k_tr_check(const double* __restrict__ x, int64_t n, TrCtl* ctl, int64_t k) {
+  __shared__ double red[1024];
+  if (ctl->done) return;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) acc += x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double s = red[0];
+    const double v = ctl->exact ? sqrt(fmax(s + ctl->rest, 0.0)) : sqrt(fmax(s, 0.0));
+    ctl->hist[k % kTrHist] = v;
+    if (!isfinite(v)) {
+      ctl->bad = 1;
+      ctl->done = k;
+    } else {
+      const bool stop = ctl->exact ? fabs(v - ctl->prev) < ctl->tol : v < ctl->tol;
+      ctl->prev = v;
+      if (stop) ctl->done = k;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_tr_values(TrDev t, const T* __restrict__ u, double* __restrict__ out) {
   const int64_t e = blockIdx.x;
@@ -293,7 +356,7 @@ hipError_t launch_tr_load(const TrDev& t, bool with_exact, hipStream_t st) {
 }
 
 template <typename T, int D, int P>
-static hipError_t sweep_impl(const TrDev& t, int src, bool to_exact, int slot, hipStream_t st) {
+static hipError_t sweep_impl(const TrDev& t, int src, bool to_exact, int64_t k, hipStream_t st) {
   using S = TrSz<D, P>;
   unsigned blocks;
   if constexpr (S::Np > 16) {
@@ -305,25 +368,25 @@ static hipError_t sweep_impl(const TrDev& t, int src, bool to_exact, int slot, h
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tr_sum, dim3(1), dim3(1024), 0, st, t.epart, static_cast<int64_t>(blocks), t.scal + slot);
+  hipLaunchKernelGGL(k_tr_check, dim3(1), dim3(1024), 0, st, t.epart, static_cast<int64_t>(blocks), t.ctl, k);
   return hipGetLastError();
 }
 
 template <typename T, int D>
-static hipError_t sweep_p(const TrDev& t, int src, bool to_exact, int slot, hipStream_t st) {
+static hipError_t sweep_p(const TrDev& t, int src, bool to_exact, int64_t k, hipStream_t st) {
   switch (t.p) {
-    case 1: return sweep_impl<T, D, 1>(t, src, to_exact, slot, st);
-    case 2: return sweep_impl<T, D, 2>(t, src, to_exact, slot, st);
-    case 3: return sweep_impl<T, D, 3>(t, src, to_exact, slot, st);
-    case 4: return sweep_impl<T, D, 4>(t, src, to_exact, slot, st);
+    case 1: return sweep_impl<T, D, 1>(t, src, to_exact, k, st);
+    case 2: return sweep_impl<T, D, 2>(t, src, to_exact, k, st);
+    case 3: return sweep_impl<T, D, 3>(t, src, to_exact, k, st);
+    case 4: return sweep_impl<T, D, 4>(t, src, to_exact, k, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_tr_sweep(const TrDev& t, int src, bool to_exact, int slot, hipStream_t st) {
-  if (t.prec == 32) return t.d == 2 ? sweep_p<float, 2>(t, src, to_exact, slot, st)
-                                    : sweep_p<float, 3>(t, src, to_exact, slot, st);
-  return t.d == 2 ? sweep_p<double, 2>(t, src, to_exact, slot, st) : sweep_p<double, 3>(t, src, to_exact, slot, st);
+hipError_t launch_tr_iterate(const TrDev& t, int src, bool to_exact, int64_t k, hipStream_t st) {
+  if (t.prec == 32) return t.d == 2 ? sweep_p<float, 2>(t, src, to_exact, k, st)
+                                    : sweep_p<float, 3>(t, src, to_exact, k, st);
+  return t.d == 2 ? sweep_p<double, 2>(t, src, to_exact, k, st) : sweep_p<double, 3>(t, src, to_exact, k, st);
 }
 
 bool tr_uses_mma(int Np) { return Np > 16; }
@@ -332,7 +395,7 @@ int tr_k_steps(int Np) { return (Np + 3) / 4; }
 
 int tr_sweep_blocks(const TrDev& t) {
   const int Np = t.Np;
-  const int epb = tr_uses_mma(Np) ? 16 : (Np >= 256 ? 1 : 256 / Np);   // the FP64 tile: the smaller count
+  const int epb = tr_uses_mma(Np) ? 32 : (Np >= 256 ? 1 : 256 / Np);   // the FP64 tile: the smaller count
   return static_cast<int>((t.E + epb - 1) / epb);
 }
 

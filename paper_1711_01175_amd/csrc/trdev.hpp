@@ -8,6 +8,20 @@
 
 namespace ewdg {
 
+// Stopping-rule state of a solve, kept on the device so that iterations can
+// be queued in batches: the check after each sweep records the norm and sets
+// done once the rule holds, and the sweeps queued after that return at once.
+constexpr int kTrHist = 64;              // ring of per-iteration norms (iteration k at k % kTrHist)
+struct TrCtl {
+  int64_t done = 0;                      // 0 while iterating, else the stopping iteration
+  int64_t bad = 0;                       // 1 if that iteration's norm was not finite
+  int64_t exact = 0;                     // 1: norm = ||u^k - u^e||, stop on its change; 0: ||u^k - u^{k-1}||
+  double prev = 0;                       // the previous iteration's norm
+  double rest = 0;                       // sum of J ||u^e - projection||^2 (exact mode)
+  double tol = 0;
+  double hist[kTrHist] = {};
+};
+
 // Elements are numbered e = i_0 + n i_1 + n^2 i_2.  Np = (p+1)^d modal
 // coefficients per element (orthonormal Legendre tensor basis), Nq = (p+3)^d
 // volume points and Nqf = (p+3)^(d-1) points per face.
@@ -34,13 +48,15 @@ struct TrDev {
   double* rest = nullptr;                // FP64 [2][E] J ||u^e - projection||^2_K, J ||u^e||^2_K
   double* epart = nullptr;               // FP64 [blocks] partial squared norms
   double* scal = nullptr;                // FP64 [8]
+  TrCtl* ctl = nullptr;
 };
 
 hipError_t launch_tr_load(const TrDev& t, bool with_exact, hipStream_t st);
-// u[dst] = c + sum over inflow axes of G_a u[src](neighbour); scal[slot] =
-// sum over elements of J ||u[dst] - target||^2 with target = uep (to_exact)
-// or u[src].
-hipError_t launch_tr_sweep(const TrDev& t, int src, bool to_exact, int slot, hipStream_t st);
+// Iteration k of a solve, skipped once ctl->done is set: u[dst] = c + sum
+// over inflow axes of G_a u[src](neighbour), then the stopping rule on the sum
+// over elements of J ||u[dst] - target||^2 with target = uep (to_exact) or
+// u[src].
+hipError_t launch_tr_iterate(const TrDev& t, int src, bool to_exact, int64_t k, hipStream_t st);
 hipError_t launch_tr_values(const TrDev& t, int src, double* out, hipStream_t st);
 hipError_t launch_tr_zero(const TrDev& t, int which, hipStream_t st);
 int tr_sweep_blocks(const TrDev& t);

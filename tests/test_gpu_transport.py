@@ -80,3 +80,31 @@ def test_stopping_on_the_change_without_exact_solution():
     T2, _, _ = _gpu(3, 2, 5, 64)
     T2.solve(1e-10, 1000)
     assert np.array_equal(got, T2.values())
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_iteration_cap_and_repeated_solves(prec):
+    """Iterations are queued in batches of 1, 2, 4, ...: a cap inside and at
+    the end of a batch stops at exactly that many sweeps (values and history
+    as the oracle's after that many), and solving again starts afresh."""
+    from oracle.transport import Transport as OT
+    d, p, n = 3, 2, 6
+    ue, f, b = smooth(d)
+    o = OT(d, p, n, b)
+    T, _, xv = _gpu(d, p, n, prec)
+    tol = 1e-12 if prec == 64 else 1e-5
+    for cap in (1, 2, 3, 5, 7, 8):
+        iters, hist = T.solve(1e-10, cap)
+        u, oi, oh = o.solve(f, ue, ue, tol=1e-10, max_iters=cap)
+        ref = u @ o.Vq.T
+        got = T.values()
+        err = np.sqrt(np.sum((got - ref) ** 2 * o.Wq)) / np.sqrt(np.sum(ref ** 2 * o.Wq))
+        _report("transport cap", prec=prec, cap=cap, iters=iters, rel_l2=err)
+        assert iters == oi == cap and len(hist) == cap + 1
+        assert err <= tol
+        assert np.allclose(hist, oh, rtol=tol, atol=tol * oh[0])
+    iters, hist = T.solve(1e-10, 1000)
+    assert iters == d * (n - 1) + 2
+    first = T.values()
+    assert T.solve(1e-10, 1000)[0] == iters
+    assert np.array_equal(T.values(), first)
