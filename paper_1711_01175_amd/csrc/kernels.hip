@@ -42,30 +42,80 @@ struct StageArgs {
   const int32_t* bcm;   // bounded meshes: per element, 2 bits per face (1 traction-free, 2 absorbing)
 };
 
-// Exact Riemann state per wave mode at one face point (outward normal n of
-// the own element).  Returns the velocity-equation correction T* - T^- and
-// the velocity jump v* - v^- that drives the strain correction.
+// Exact Riemann solution per wave mode at one face point (outward normal n
+// of the own element): the normal (P) mode carries J_p = (dT.n + Z_p+ dv.n)
+// / (Z_p- + Z_p+) and the tangential (S) mode j_t = ((dT + Z_s+ dv) minus
+// its normal part) / (Z_s- + Z_s+), with the jumps dT = T+ - T- (tractions)
+// and dv = v+ - v-.  Out, scaled by the face factor fs: fl[0..2] = fs (T* -
+// T-) = fs (Z_s- j_t + Z_p- J_p n) (velocity equation) and fl[3..8] = the
+// strain correction sym(n (x) (v* - v-)) with v* - v- = j_t + J_p n, as the
+// rows xx, yy, zz, yz, xz, xy.
+//
+// FP32 forms the jumps first (about half the vector instructions of the
+// per-state form, and the hardware reciprocal); FP64 projects each side's
+// state onto the normal and tangential modes first, which measured faster
+// there (the FP64 stage is register-bound at two waves per SIMD).
 template <typename T>
-__device__ __forceinline__ void interface_state(const T* n, const T* vm, const T* Tm, const T* vp,
-                                                 const T* Tp, T zpm, T zpp, T zsm, T zsp,
-                                                 T* dT, T* dv) {
-  const T vmn = vm[0] * n[0] + vm[1] * n[1] + vm[2] * n[2];
-  const T vpn = vp[0] * n[0] + vp[1] * n[1] + vp[2] * n[2];
-  const T Tmn = Tm[0] * n[0] + Tm[1] * n[1] + Tm[2] * n[2];
-  const T Tpn = Tp[0] * n[0] + Tp[1] * n[1] + Tp[2] * n[2];
-  const T ip = T(1) / (zpm + zpp);
-  const T is = T(1) / (zsm + zsp);
-  // normal mode: T*_n - T^-_n and v*_n - v^-_n
-  const T dTn = zpm * ((Tpn - Tmn) + zpp * (vpn - vmn)) * ip;
-  const T dvn = ((Tpn - Tmn) + zpp * (vpn - vmn)) * ip;
-  // tangential modes
+__device__ __forceinline__ void interface_flux(const T* n, T fs, const T* vm, const T* sm, const T* vp,
+                                               const T* sp, T zpm, T zpp, T zsm, T zsp, T* fl) {
+  if constexpr (sizeof(T) == 4) {
+    T ds[6], dv[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const T vmt = vm[c] - vmn * n[c], vpt = vp[c] - vpn * n[c];
-    const T Tmt = Tm[c] - Tmn * n[c], Tpt = Tp[c] - Tpn * n[c];
-    const T jt = (Tpt - Tmt) + zsp * (vpt - vmt);
-    dT[c] = zsm * jt * is + dTn * n[c];
-    dv[c] = jt * is + dvn * n[c];
+    for (int m = 0; m < 6; ++m) ds[m] = sp[m] - sm[m];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dv[c] = vp[c] - vm[c];
+    const T dT[3] = {ds[0] * n[0] + ds[5] * n[1] + ds[4] * n[2], ds[5] * n[0] + ds[1] * n[1] + ds[3] * n[2],
+                     ds[4] * n[0] + ds[3] * n[1] + ds[2] * n[2]};
+    const T dTn = dT[0] * n[0] + dT[1] * n[1] + dT[2] * n[2];
+    const T dvn = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
+    const T ip = fs * __builtin_amdgcn_rcpf(zpm + zpp), is = fs * __builtin_amdgcn_rcpf(zsm + zsp);
+    const T jp = (dTn + zpp * dvn) * ip;      // fs J_p
+    const T jsn = dTn + zsp * dvn;            // normal part of dT + Z_s+ dv
+    const T tp = zpm * jp;
+    T fv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T jt = (dT[c] + zsp * dv[c] - jsn * n[c]) * is;   // fs j_t
+      fl[c] = zsm * jt + tp * n[c];
+      fv[c] = jt + jp * n[c];
+    }
+    fl[3] = n[0] * fv[0];
+    fl[4] = n[1] * fv[1];
+    fl[5] = n[2] * fv[2];
+    fl[6] = T(0.5) * (n[1] * fv[2] + n[2] * fv[1]);
+    fl[7] = T(0.5) * (n[0] * fv[2] + n[2] * fv[0]);
+    fl[8] = T(0.5) * (n[0] * fv[1] + n[1] * fv[0]);
+  } else {
+    const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2], sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
+                     sm[4] * n[0] + sm[3] * n[1] + sm[2] * n[2]};
+    const T Tp[3] = {sp[0] * n[0] + sp[5] * n[1] + sp[4] * n[2], sp[5] * n[0] + sp[1] * n[1] + sp[3] * n[2],
+                     sp[4] * n[0] + sp[3] * n[1] + sp[2] * n[2]};
+    const T vmn = vm[0] * n[0] + vm[1] * n[1] + vm[2] * n[2];
+    const T vpn = vp[0] * n[0] + vp[1] * n[1] + vp[2] * n[2];
+    const T Tmn = Tm[0] * n[0] + Tm[1] * n[1] + Tm[2] * n[2];
+    const T Tpn = Tp[0] * n[0] + Tp[1] * n[1] + Tp[2] * n[2];
+    const T ip = T(1) / (zpm + zpp);
+    const T is = T(1) / (zsm + zsp);
+    const T dTn = zpm * ((Tpn - Tmn) + zpp * (vpn - vmn)) * ip;   // Z_p- J_p
+    const T dvn = ((Tpn - Tmn) + zpp * (vpn - vmn)) * ip;         // J_p
+    T dT[3], dv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T vmt = vm[c] - vmn * n[c], vpt = vp[c] - vpn * n[c];
+      const T Tmt = Tm[c] - Tmn * n[c], Tpt = Tp[c] - Tpn * n[c];
+      const T jt = (Tpt - Tmt) + zsp * (vpt - vmt);
+      dT[c] = zsm * jt * is + dTn * n[c];
+      dv[c] = jt * is + dvn * n[c];
+    }
+    fl[0] = fs * dT[0];
+    fl[1] = fs * dT[1];
+    fl[2] = fs * dT[2];
+    fl[3] = fs * n[0] * dv[0];
+    fl[4] = fs * n[1] * dv[1];
+    fl[5] = fs * n[2] * dv[2];
+    fl[6] = fs * T(0.5) * (n[1] * dv[2] + n[2] * dv[1]);
+    fl[7] = fs * T(0.5) * (n[0] * dv[2] + n[2] * dv[0]);
+    fl[8] = fs * T(0.5) * (n[0] * dv[1] + n[1] * dv[0]);
   }
 }
 
@@ -400,21 +450,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         sp = spx;
         vp = vpx;
       }
-      const T Tm[3] = {sm[0] * n[0] + sm[5] * n[1] + sm[4] * n[2], sm[5] * n[0] + sm[1] * n[1] + sm[3] * n[2],
-                       sm[4] * n[0] + sm[3] * n[1] + sm[2] * n[2]};
-      const T Tp[3] = {sp[0] * n[0] + sp[5] * n[1] + sp[4] * n[2], sp[5] * n[0] + sp[1] * n[1] + sp[3] * n[2],
-                       sp[4] * n[0] + sp[3] * n[1] + sp[2] * n[2]};
-      T dT[3], dv[3];
-      interface_state(n, vm, Tm, vp, Tp, gg[25], pt.zp, gg[26], pt.zs, dT, dv);
-      fl[0 * 16] = fs * dT[0];
-      fl[1 * 16] = fs * dT[1];
-      fl[2 * 16] = fs * dT[2];
-      fl[3 * 16] = fs * n[0] * dv[0];
-      fl[4 * 16] = fs * n[1] * dv[1];
-      fl[5 * 16] = fs * n[2] * dv[2];
-      fl[6 * 16] = fs * T(0.5) * (n[1] * dv[2] + n[2] * dv[1]);
-      fl[7 * 16] = fs * T(0.5) * (n[0] * dv[2] + n[2] * dv[0]);
-      fl[8 * 16] = fs * T(0.5) * (n[0] * dv[1] + n[1] * dv[0]);
+      T flx[9];
+      interface_flux(n, fs, vm, sm, vp, sp, gg[25], pt.zp, gg[26], pt.zs, flx);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) fl[c * 16] = flx[c];
     }
     if (fn < 4) gather(fn, pf);   // in flight during the lift(s) before its flux
     __syncthreads();
