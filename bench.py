@@ -610,6 +610,8 @@ def main():
     ap.add_argument("--no-transport", action="store_true", help="skip the steady transport (iHDG-II) leg")
     ap.add_argument("--wadg-only", action="store_true",
                     help="run only the weight-adjusted mass inverse leg and print its JSON (for profiling)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg (full stream unless --serving-reduced) and print its JSON")
     ap.add_argument("--transport-only", action="store_true",
                     help="run only the steady transport leg and print its JSON (for profiling)")
     ap.add_argument("--implicit-only", action="store_true",
@@ -645,6 +647,9 @@ def main():
         return
     if args.transport_only:
         print(json.dumps({"transport": run_transport()}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": run_serving(not args.serving_reduced)}), flush=True)
         return
     if args.wadg_only:
         print(json.dumps({"weight_adjusted": run_wadg()}), flush=True)

@@ -2,8 +2,10 @@
 
 Requests (a mesh, degree, medium, source and step count each) arrive over
 time.  A request is admitted as soon as a slot is free and its exact device
-footprint (ewdg_workspace_bytes) fits in the remaining HBM budget; its state
-then stays on the device until it retires.  All admitted requests advance
+footprint (ewdg_workspace_bytes) fits in the remaining HBM budget, in arrival
+order, except that a later request may pass a head that does not fit if it
+cannot delay that head (backfilling, admit_backfill); its state then stays on
+the device until it retires.  All admitted requests advance
 together through ewdg_step_batch: each LSRK stage is one ragged launch per
 degree class over every active request's elements, so requests that arrive
 while others run join the same launches at the next chunk boundary.  Each
@@ -33,26 +35,57 @@ import numpy as np
 from . import ewdg as B
 
 
-def admit_fifo(waiting, n_active, used_bytes, slots, budget):
-    """First-in first-out admission.
+def admit_backfill(waiting, n_active, used_bytes, slots, budget, releases=()):
+    """First-in first-out admission with backfilling.
 
-    waiting: sequence of (key, footprint_bytes).  Returns (admitted keys,
-    rejected keys): a request is admitted while a slot is free and its
-    footprint fits in the remaining budget; the head of the queue blocks the
-    ones behind it.  A request larger than the whole budget is rejected.
+    waiting: sequence of (key, footprint_bytes) in arrival order; releases:
+    (steps_left, footprint_bytes) of every running request (all of them
+    advance together, so they retire in the order of their steps left).
+    Returns (admitted keys, rejected keys).  Requests are admitted in order
+    while a slot is free and the footprint fits in the remaining budget.  When
+    the head of the queue does not fit, it holds a reservation: the first
+    retirement after which the memory and the slot it needs are free.  A
+    request behind it is admitted now only if it fits now and what it takes
+    still leaves the reservation intact (it is assumed to run past it), so the
+    head is never delayed by a request that arrived after it.  Only the head
+    holds a reservation: a request further back can start a little later than
+    under strict arrival order, while on average requests start earlier.  A
+    request larger than the whole budget is rejected.
     """
     admitted, rejected = [], []
     free_slots = slots - n_active
     free_bytes = budget - used_bytes
+    spare = None               # (bytes, slots) left over at the head's reservation
     for key, fp in waiting:
         if fp > budget:
             rejected.append(key)
             continue
-        if free_slots <= 0 or fp > free_bytes:
-            break
-        admitted.append(key)
-        free_slots -= 1
-        free_bytes -= fp
+        if spare is None:
+            if free_slots > 0 and fp <= free_bytes:
+                admitted.append(key)
+                free_slots -= 1
+                free_bytes -= fp
+                continue
+            # the head waits: memory and slots at its reservation
+            fb, fs = free_bytes, free_slots
+            spare = (0, 0)
+            rel = sorted(releases)
+            i = 0
+            while i < len(rel):
+                left = rel[i][0]
+                while i < len(rel) and rel[i][0] == left:
+                    fb += rel[i][1]
+                    fs += 1
+                    i += 1
+                if fb >= fp and fs >= 1:
+                    spare = (fb - fp, fs - 1)
+                    break
+            continue
+        if free_slots > 0 and fp <= free_bytes and fp <= spare[0] and spare[1] >= 1:
+            admitted.append(key)
+            free_slots -= 1
+            free_bytes -= fp
+            spare = (spare[0] - fp, spare[1] - 1)
     return admitted, rejected
 
 
@@ -249,7 +282,7 @@ class Server:
         stats = ServeStats()
         total = len(requests)
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
-        waiting, active = deque(), []      # waiting: futures of prepared requests, FIFO
+        waiting, active = deque(), []      # waiting: futures of requests in preparation, arrival order
         inflight = deque()                 # (event, requests, steps, guard buffer) per queued chunk
         used = 0
         t0 = clock()
@@ -278,15 +311,18 @@ class Server:
                     a.sched += chunk
                     a.inflight += 1
                 inflight.append((ev, launch, chunk, gb))
-            # admission in arrival order among prepared requests (the head of
-            # the queue blocks the ones behind it until it is prepared)
+            # admission among prepared requests in arrival order, with
+            # backfilling behind a head that does not fit (the first request
+            # not yet prepared ends the list)
             ready = []
             for f in waiting:
                 if not f.done():
                     break
                 ready.append(f.result())
-            adm, rej = admit_fifo([(id(w), w.footprint) for w in ready], len(active), used,
-                                  self.slots, self.budget)
+            releases = [(a.req.nsteps - a.done, a.footprint) for a in active]
+            adm, rej = admit_backfill([(id(w), w.footprint) for w in ready], len(active), used,
+                                      self.slots, self.budget, releases)
+            adm, rej = set(adm), set(rej)
             admitted = []
             for w in ready:
                 if id(w) in rej:
@@ -298,10 +334,9 @@ class Server:
                         on_admit(w.req.rid, w.ctx)
                     used += w.footprint
                     admitted.append(w)
-                else:
-                    break
-            for _ in range(sum(1 for w in ready if id(w) in rej or id(w) in adm)):
-                waiting.popleft()
+            if adm or rej:
+                taken = adm | rej
+                waiting = deque(f for i, f in enumerate(waiting) if i >= len(ready) or id(ready[i]) not in taken)
             for w in admitted:
                 if w.req.nsteps <= 0:          # nothing to run: retire at once
                     self._finish(w, clock() - t0, stats)

@@ -1,20 +1,96 @@
 """Host-side checks of the serving loop's admission policy and request stream."""
 import numpy as np
 
-from paper_1711_01175_amd.serving import admit_fifo
+from paper_1711_01175_amd.serving import admit_backfill
 from workloads.requests import request_stream
 
 
 def test_admission_respects_slots_budget_and_order():
     waiting = [("a", 4), ("b", 3), ("c", 1), ("d", 2)]
-    adm, rej = admit_fifo(waiting, n_active=0, used_bytes=0, slots=8, budget=8)
+    adm, rej = admit_backfill(waiting, n_active=0, used_bytes=0, slots=8, budget=8)
     assert adm == ["a", "b", "c"] and rej == []          # d would overflow the budget
-    adm, rej = admit_fifo(waiting, n_active=6, used_bytes=0, slots=8, budget=100)
+    adm, rej = admit_backfill(waiting, n_active=6, used_bytes=0, slots=8, budget=100)
     assert adm == ["a", "b"]                               # two free slots
-    adm, rej = admit_fifo(waiting, n_active=0, used_bytes=5, slots=8, budget=8)
-    assert adm == []                                       # head of line blocks
-    adm, rej = admit_fifo([("x", 20), ("y", 2)], 0, 0, 4, 10)
+    adm, rej = admit_backfill(waiting, n_active=0, used_bytes=5, slots=8, budget=8)
+    assert adm == []                                       # nothing running retires: no backfill
+    adm, rej = admit_backfill([("x", 20), ("y", 2)], 0, 0, 4, 10)
     assert rej == ["x"] and adm == ["y"]                   # larger than the whole budget
+
+
+def test_backfilling_never_delays_the_head():
+    """budget 10, two running requests of 4 bytes each (5 and 20 steps
+    left): a head of 6 fits once the first retires, with nothing to spare, so
+    nothing passes it; a head of 5 leaves 1 byte spare at its reservation, so
+    only a request of 1 byte that fits now may pass."""
+    running = [(5, 4), (20, 4)]
+    adm, _ = admit_backfill([("big", 6), ("small", 2), ("tiny", 1)], 2, 8, 8, 10, running)
+    assert adm == []
+    adm, _ = admit_backfill([("big", 5), ("small", 2), ("tiny", 1)], 2, 8, 8, 10, running)
+    assert adm == ["tiny"]
+    # a head that needs both retirements: 2 + 4 + 4 = 10 free then, 1 spare
+    adm, _ = admit_backfill([("huge", 9), ("small", 2), ("tiny", 1), ("tiny2", 1)], 2, 8, 8, 10, running)
+    assert adm == ["tiny"]
+    # slots: 3 slots, 2 running; the head's reservation needs the slot freed
+    # by the first retirement and the free slot stays spare
+    adm, _ = admit_backfill([("big", 5), ("tiny", 1), ("tiny2", 1)], 2, 8, 3, 10, running)
+    assert adm == ["tiny"]
+    adm, _ = admit_backfill([("big", 5), ("tiny", 1)], 3, 8, 3, 10, running + [(30, 0)])
+    assert adm == []                                       # no free slot now
+    # requests retiring in the same chunk free their memory together
+    adm, _ = admit_backfill([("big", 8), ("tiny", 2)], 2, 8, 8, 10, [(5, 4), (5, 4)])
+    assert adm == ["tiny"]
+
+
+def test_backfilling_in_a_simulated_serving_loop():
+    """A small simulation of the serving loop (every running request advances
+    one step per tick, 6 slots, 8 bytes): at every tick where the head of the
+    queue waits, the requests admitted past it leave its reservation intact
+    (replaying the running requests' retirements with them included frees
+    the head's memory and slot no later than without them); over the whole
+    stream requests start earlier than under strict arrival order, on
+    average and at worst, and the stream ends no later."""
+    import random
+    rng = random.Random(5)
+    reqs = [(i, rng.choice([1, 2, 3, 6]), rng.randint(3, 12)) for i in range(40)]   # (id, bytes, steps)
+    slots, budget = 6, 8
+
+    def fits_at(running, fp):
+        """ticks until fp bytes and a slot are free, if nothing else is admitted"""
+        free_b, free_s = budget - sum(r[1] for r in running), slots - len(running)
+        for t, grp in enumerate(sorted({r[2] for r in running})):
+            if free_b >= fp and free_s >= 1:
+                return 0 if t == 0 else prev
+            free_b += sum(r[1] for r in running if r[2] == grp)
+            free_s += sum(1 for r in running if r[2] == grp)
+            prev = grp
+        return prev if running else 0
+
+    def simulate(backfill):
+        waiting, running, start, t = list(reqs), [], {}, 0
+        while waiting or running:
+            used = sum(r[1] for r in running)
+            rel = [(r[2], r[1]) for r in running] if backfill else []
+            adm, _ = admit_backfill([(r[0], r[1]) for r in waiting], len(running), used, slots, budget, rel)
+            head = next((w for w in waiting if w[0] not in adm), None)
+            passed = [w for w in waiting if w[0] in adm and head is not None and w[0] > head[0]]
+            if passed:
+                before = fits_at(running, head[1])
+                after = fits_at(running + [[w[0], w[1], 10 ** 6] for w in passed], head[1])
+                assert after <= before, (t, head, passed)
+            for r in [w for w in waiting if w[0] in adm]:
+                start[r[0]] = t
+                running.append([r[0], r[1], r[2]])
+            waiting = [w for w in waiting if w[0] not in adm]
+            for r in running:
+                r[2] -= 1
+            running = [r for r in running if r[2] > 0]
+            t += 1
+        return start, t
+
+    (fifo, t_fifo), (bf, t_bf) = simulate(False), simulate(True)
+    assert sum(bf.values()) < sum(fifo.values())
+    assert max(bf.values()) <= max(fifo.values())
+    assert t_bf <= t_fifo
 
 
 def test_request_stream_is_seeded_and_poisson():
