@@ -116,3 +116,15 @@ def test_energy_guard_decisions():
     assert energy_check(1.0, float("nan"), 1e6) == "non-finite energy"
     assert energy_check(0.0, float("inf"), 1e6) == "non-finite energy"
     assert energy_check(1.0, 1e30, None) is None
+
+
+def test_media_sampled_with_torch_match_numpy():
+    """The server samples media through torch's CPU kernels: the same
+    formula as the numpy path, equal to within rounding."""
+    import torch
+    from workloads import media
+    x = np.random.default_rng(3).uniform(-1, 1, size=(500, 11, 3))
+    kw = dict(phases=(0.1, 0.2, 0.3, 0.4), amps=(1.1, 0.9, 1.2))
+    for a, b in zip(media.smooth(x, **kw), media.smooth(torch.from_numpy(x), **kw)):
+        assert isinstance(b, torch.Tensor) and b.dtype == torch.float64
+        assert np.allclose(a, b.numpy(), rtol=4e-16, atol=0)

@@ -1,7 +1,8 @@
 """Material fields (rho, lambda, mu) as closed-form functions of position.
 
 All functions take xyz with shape [..., 3] (for example the physical
-quadrature points [K][Nq][3]) and return arrays of shape [...].  The smooth
+quadrature points [K][Nq][3]) and return arrays of shape [...].  smooth also
+takes a torch tensor and then returns torch tensors (the same formula).  The smooth
 fields are 1-periodic, hence periodic on [-1,1]^3.
 """
 import numpy as np
@@ -22,13 +23,21 @@ def smooth(xyz, phases=(0.0, 0.0, 0.0, 0.0, 0.0), amps=(1.0, 1.0, 1.0)):
     rho = 1 + 0.3 a_rho sin(2 pi (x + y + z) + p3)
     Default phases 0 and amplitude factors 1 give the reference medium.
     """
+    xp = np if isinstance(xyz, np.ndarray) else _array_module(xyz)
     x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
     p0, p1, p2, p3 = phases[:4]
     a_rho, a_lam, a_mu = amps
-    mu = 1.0 + 0.5 * a_mu * np.sin(TWO_PI * x + p0) * np.cos(TWO_PI * y + p1)
-    lam = 2.0 + 0.5 * a_lam * np.cos(TWO_PI * z + p2)
-    rho = 1.0 + 0.3 * a_rho * np.sin(TWO_PI * (x + y + z) + p3)
+    mu = 1.0 + 0.5 * a_mu * xp.sin(TWO_PI * x + p0) * xp.cos(TWO_PI * y + p1)
+    lam = 2.0 + 0.5 * a_lam * xp.cos(TWO_PI * z + p2)
+    rho = 1.0 + 0.3 * a_rho * xp.sin(TWO_PI * (x + y + z) + p3)
     return rho, lam, mu
+
+
+def _array_module(a):
+    """numpy, or torch for a torch tensor (its CPU kernels run on several
+    threads: the server samples large media that way)."""
+    import torch
+    return torch if isinstance(a, torch.Tensor) else np
 
 
 def perturb_per_element(rho, lam, mu, seed, frac=0.1):
