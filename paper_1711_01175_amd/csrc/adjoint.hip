@@ -123,7 +123,7 @@ __device__ __forceinline__ void load_geo(const AdjArgs<T>& a, int64_t e0, int ne
     T v;
     if (m < 9) v = a.geo[(e0 + e) * 9 + m];
     else if (m < 25) v = a.fgeo[(e0 + e) * 16 + (m - 9)];
-    else v = a.Z[(e0 + e) * 2 + (m - 25)];
+    else v = a.Z[(e0 + e) * kZS + (m - 25)];
     sg[e * 32 + m] = v;
   }
 }
@@ -174,7 +174,7 @@ __global__ __launch_bounds__((AdjCfg<T, N>::NT)) void k_adjA(AdjArgs<T> a) {
     const int32_t wd = a.conn[(e0 + e) * 4 + f];
     const int64_t nb = wd >> 5;
     const int code = wd & 31;
-    const T zpm = gg[25], zsm = gg[26], zpp = a.Z[nb * 2], zsp = a.Z[nb * 2 + 1];
+    const T zpm = gg[25], zsm = gg[26], zpp = a.Z[nb * kZS], zsp = a.Z[nb * kZS + 1];
     T D[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) D[c] = 0;
@@ -516,7 +516,7 @@ __global__ __launch_bounds__((Tile<N>::NT), EWDG_ADJ_OCC) void k_adjB_mma(AdjArg
     if (e < ne) {
       if (m < 9) v = a.geo[(e0 + e) * 9 + m];
       else if (m < 25) v = a.fgeo[(e0 + e) * 16 + (m - 9)];
-      else v = a.Z[(e0 + e) * 2 + (m - 25)];
+      else v = a.Z[(e0 + e) * kZS + (m - 25)];
     }
     sgeo[e * 32 + m] = v;
   }

@@ -130,7 +130,7 @@ size_t layout(ewdg_ctx* c, char* base) {
   d.lm = take(2 * ((Nq + 3) / 4 * 4) * K * ts);
   d.geo = take(9 * K * ts);
   d.fgeo = take(16 * K * ts);
-  d.Z = take(2 * K * ts);
+  d.Z = take(kZS * K * ts);
   d.svec = take(Np * ts);
   const size_t NpR = pad_to(Np, 16), NpK = pad_to(Np, 4), NqR = pad_to(Nq, 16), NqK = pad_to(Nq, 4),
                NfpK = pad_to(Nfp, 4);

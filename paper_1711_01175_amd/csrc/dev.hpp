@@ -7,6 +7,10 @@
 
 namespace ewdg {
 
+// Impedances per element: own (Z_p, Z_s), then the neighbour's pair across
+// each of the four faces (on a boundary face, the element's own pair).
+constexpr int kZS = 10;
+
 // All pointers live inside the caller's workspace.  "Run precision" arrays
 // are float or double according to prec; the others are FP64 or int32.
 struct Dev {
@@ -20,7 +24,7 @@ struct Dev {
   void* lm = nullptr;                // [K][2][NqP] lambda, mu at quadrature points (NqP = Nq rounded up to 4, zero padded)
   void* geo = nullptr;               // [K][9] dr_i/dx_j
   void* fgeo = nullptr;              // [K][4][4] n_x, n_y, n_z, Fscale
-  void* Z = nullptr;                 // [K][2] Z_p, Z_s
+  void* Z = nullptr;                 // [K][kZS]: own Z_p, Z_s, then the neighbour's Z_p, Z_s across faces 0..3
   void* svec = nullptr;              // [Np] source vector M_rho^-1 phi(x_s)
   // operators in matrix-core fragment order (see the stage kernel):
   // [row tile][k-step][64 lanes], zero padded

@@ -132,7 +132,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
 // tile does not keep them in LDS.
 template <typename T>
 struct FacePt {
-  T sm[6], vp[3], sp[6], zp, zs;
+  T sm[6], vp[3], sp[6];
 };
 
 template <typename T, int N, int MODE, bool BND = false, bool WADG = false>
@@ -143,7 +143,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   constexpr int Np = TL::Np, Nfp = TL::Nfp, Nq = TL::Nq, E = TL::E;
   constexpr int NpK = TL::NpK, NqK = TL::NqK, NfpK = TL::NfpK;
   constexpr int RT = TL::RT, QT = TL::QT, NW = TL::NW, NT = TL::NT;
-  constexpr int SV = TL::SV, SE = TL::SE, SF = TL::SF, SQ = TL::SQ;
+  constexpr int SV = TL::SV, SE = TL::SE, SF = TL::SF, SQ = TL::SQ, GS = TL::GS;
   constexpr int KD = NpK / 4, KF = NfpK / 4;       // k-steps of the node / face contractions
   // Operator fragments of the node contractions are held in groups of GK
   // k-steps, two groups at a time, where all KD would crowd the registers
@@ -243,8 +243,6 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         for (int c = 0; c < 3; ++c) pt.vp[c] = qn[c * Np];
 #pragma unroll
         for (int m = 0; m < 6; ++m) pt.sp[m] = sn[m * Np];
-        pt.zp = a.Z[nb * 2];
-        pt.zs = a.Z[nb * 2 + 1];
       }
     }
   };
@@ -259,18 +257,23 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   T* Sv = sX;                // [NpK][SV]  v_c of element e at column c*16+e
   T* SG = sX + NpK * SV;     // [NpK][SV]  G^k_c for the current direction k
   {
-    constexpr int NGL = (E * 27 + NT - 1) / NT;
+    constexpr int NGV = 27;   // geometry and own impedances per element
+    constexpr int NGL = (E * NGV + NT - 1) / NT;
     constexpr int NVL = (E * 3 * Np + NT - 1) / NT;
     constexpr int NSL = SIGL ? (E * 6 * Np + NT - 1) / NT : 1;
     T gv0[NGL], vv[NVL], sv[NSL];
 #pragma unroll
     for (int p = 0; p < NGL; ++p) {
       const int x = tid + p * NT;
-      const int e = x / 27, m = x % 27;
+      const int e = x / NGV, m = x % NGV;
       const int ge = e0 + e < Ke ? e0 + e : Ke - 1;
-      const T* src = m < 9 ? a.geo + ge * 9 + m : (m < 25 ? a.fgeo + ge * 16 + (m - 9) : a.Z + ge * 2 + (m - 25));
-      gv0[p] = x < E * 27 ? *src : T(0);
+      const T* src = m < 9 ? a.geo + ge * 9 + m : (m < 25 ? a.fgeo + ge * 16 + (m - 9) : a.Z + ge * kZS + (m - 25));
+      gv0[p] = x < E * NGV ? *src : T(0);
     }
+    // the neighbours' impedances across the four faces (8 values per element)
+    static_assert(E * 8 <= NT, "one neighbour impedance per thread");
+    const int ze = tid / 8, zm = tid % 8;
+    const T znb = tid < E * 8 ? a.Z[(e0 + ze < Ke ? e0 + ze : Ke - 1) * kZS + 2 + zm] : T(0);
 #pragma unroll
     for (int p = 0; p < NVL; ++p) {
       const int x = tid + p * NT;
@@ -295,9 +298,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
     for (int p = 0; p < NGL; ++p) {
       const int x = tid + p * NT;
-      const int e = x / 27, m = x % 27;
-      if (x < E * 27) sgeo[e * 32 + m] = e0 + e < Ke ? gv0[p] : T(0);
+      const int e = x / NGV, m = x % NGV;
+      if (x < E * NGV) sgeo[e * GS + m] = e0 + e < Ke ? gv0[p] : T(0);
     }
+    if (tid < E * 8) sgeo[ze * GS + NGV + zm] = znb;
 #pragma unroll
     for (int p = 0; p < NVL; ++p) {
       const int x = tid + p * NT;
@@ -326,7 +330,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   acc_t rhs[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) rhs[c] = acc_t{0, 0, 0, 0};
-  const T* gl = &sgeo[lr * 32];   // geometry of this lane's element
+  const T* gl = &sgeo[lr * GS];   // geometry of this lane's element
 #pragma unroll 1
   for (int k = 0; k < 3; ++k) {
     T afA[GK], afB[GK];
@@ -350,7 +354,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
 #pragma unroll
           for (int m = 0; m < 6; ++m) sg[m] = Ssig[j * SE + m * 16 + e];
         }
-        const T* g = &sgeo[e * 32 + k * 3];
+        const T* g = &sgeo[e * GS + k * 3];
         // rows of sigma in Voigt order xx,yy,zz,yz,xz,xy
         const int es = e ^ sw(j);
         SG[j * SV + 0 * 16 + es] = g[0] * sg[0] + g[1] * sg[5] + g[2] * sg[4];
@@ -420,7 +424,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
       int il;
       if constexpr (PRE) il = (ilp[p] >> (8 * f)) & 255;
       else il = a.fmask[f * Nfp + j];
-      const T* gg = &sgeo[e * 32];
+      const T* gg = &sgeo[e * GS];
       const T n[3] = {gg[9 + f * 4 + 0], gg[9 + f * 4 + 1], gg[9 + f * 4 + 2]};
       const T fs = gg[9 + f * 4 + 3];
       T vm[3];
@@ -451,7 +455,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
         vp = vpx;
       }
       T flx[9];
-      interface_flux(n, fs, vm, sm, vp, sp, gg[25], pt.zp, gg[26], pt.zs, flx);
+      interface_flux(n, fs, vm, sm, vp, sp, gg[25], gg[27 + 2 * f], gg[26], gg[28 + 2 * f], flx);
 #pragma unroll
       for (int c = 0; c < 9; ++c) fl[c * 16] = flx[c];
     }
@@ -1053,7 +1057,7 @@ __global__ __launch_bounds__(256) void k_material(Dev d, int64_t e_begin) {
     r /= ws;
     l /= ws;
     m /= ws;
-    T* Z = static_cast<T*>(d.Z) + e * 2;
+    T* Z = static_cast<T*>(d.Z) + e * kZS;
     Z[0] = static_cast<T>(sqrt(r * (l + 2.0 * m)));
     Z[1] = static_cast<T>(sqrt(r * m));
     d.means64[e * 3 + 0] = r;
@@ -1319,9 +1323,34 @@ static void fill_args(const Dev& d, const void* qin, const void* sin, void* qout
 
 bool supported_degree(int N) { return N == 1 || N == 2 || N == 3 || N == 4 || N == 5 || N == 7; }
 
+// The neighbour's impedances across each face, next to the element's own
+// (read by the face flux of the stage kernel from the tile's geometry block
+// instead of being gathered per face point).  A boundary face's connectivity
+// names the element itself.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nbr_z(T* __restrict__ Z, const int32_t* __restrict__ conn, int64_t K) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= 4 * K) return;
+  const int64_t e = i / 4, f = i % 4;
+  const int64_t nb = conn[i] >> 5;
+  Z[e * kZS + 2 + 2 * f] = Z[nb * kZS];
+  Z[e * kZS + 3 + 2 * f] = Z[nb * kZS + 1];
+}
+
 hipError_t launch_material(const Dev& d, hipStream_t st) {
-  if (d.prec == 32) { EWDG_DISPATCH(d.N, return (material_impl<float, NN>(d, st))); }
-  EWDG_DISPATCH(d.N, return (material_impl<double, NN>(d, st)));
+  hipError_t e;
+  if (d.prec == 32) {
+    EWDG_DISPATCH(d.N, e = (material_impl<float, NN>(d, st)); break);
+  } else {
+    EWDG_DISPATCH(d.N, e = (material_impl<double, NN>(d, st)); break);
+  }
+  if (e != hipSuccess) return e;
+  const unsigned blocks = static_cast<unsigned>((4 * d.K + 255) / 256);
+  if (d.prec == 32)
+    hipLaunchKernelGGL(k_nbr_z<float>, dim3(blocks), dim3(256), 0, st, static_cast<float*>(d.Z), d.conn, d.K);
+  else
+    hipLaunchKernelGGL(k_nbr_z<double>, dim3(blocks), dim3(256), 0, st, static_cast<double*>(d.Z), d.conn, d.K);
+  return hipGetLastError();
 }
 
 hipError_t launch_source_vector(const Dev& d, int64_t elem, hipStream_t st) {

@@ -97,7 +97,10 @@ struct Tile {
   static constexpr int X = cmax2(2 * NpK * SV, NpK * SE);
   static constexpr int QC = NqR < EWDG_QC ? NqR : EWDG_QC;   // quadrature rows per chunk (whole tiles)
   static constexpr int Y = cmax2(cmax2(NfpK * SF, QC * SQ), NpK * SV);
-  static constexpr int GEO = E * 32;
+  // per element in LDS: dr/dx (9), per face n and Fscale (16), own Z_p, Z_s
+  // and the neighbour's across each face (10), padded to 36
+  static constexpr int GS = 36;
+  static constexpr int GEO = E * GS;
 };
 
 }  // namespace ewdg
