@@ -938,33 +938,101 @@ __global__ __launch_bounds__((Tile<N>::NT), (sizeof(T) == 4 ? EWDG_OCC32 : 2)) v
 }
 
 // sigma_h = P_Q(lambda tr(e) I + 2 mu e) for a given state (no update).
+// sigma_h = P_Q (lambda tr(eps_Q) I + 2 mu eps_Q), eps_Q = V_Q eps, of a
+// state q (the L2_Q projection of C eps, as in the stage kernel): 16
+// elements per workgroup on the matrix cores.  The strains sit in LDS as B
+// operands (node rows, element columns per component); V_Q runs in chunks of
+// QC quadrature rows, Hooke's law is applied at the points, and P_Q
+// accumulates across the chunks in the owner waves of the node row tiles.
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_sigma(const T* __restrict__ q, T* __restrict__ s,
-                                               const T* __restrict__ lm, const T* __restrict__ VqT,
-                                               const T* __restrict__ PqT, int64_t K) {
-  using S = Sz<N>;
-  constexpr int Np = S::Np, Nq = S::Nq;
-  __shared__ T se[6 * Np];
-  __shared__ T sg[6 * Nq];
-  const int64_t e = blockIdx.x;
-  for (int x = threadIdx.x; x < 6 * Np; x += 256) se[x] = q[e * 9 * Np + 3 * Np + x];
+__global__ __launch_bounds__((Tile<N>::NT)) void k_sigma(const T* __restrict__ q, T* __restrict__ s,
+                                                         const T* __restrict__ lm, const T* __restrict__ Vqpad,
+                                                         const T* __restrict__ Pqpad, int64_t K) {
+  using TL = Tile<N>;
+  using M = Mfma<T>;
+  using acc_t = typename M::acc_t;
+  constexpr int Np = TL::Np, Nq = TL::Nq, NqP = TL::NqP, E = TL::E, NpK = TL::NpK, NqK = TL::NqK;
+  constexpr int RT = TL::RT, QT = TL::QT, NT = TL::NT, KD = NpK / 4;
+  constexpr int SE = TL::SE, SQ = 96, QC = 64, NQC = (QT * 16 + QC - 1) / QC;
+  __shared__ T Se[NpK * SE];   // strains, then the result
+  __shared__ T Sq[QC * SQ];    // stresses at the chunk's quadrature points
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lg = l >> 4;
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * E;
+  for (int x = tid; x < E * 6 * Np; x += NT) {
+    const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, j = rem % Np;
+    Se[j * SE + m * 16 + e] = e0 + e < K ? q[(e0 + e) * 9 * Np + 3 * Np + rem] : T(0);
+  }
+  for (int x = tid; x < (NpK - Np) * SE; x += NT) Se[Np * SE + x] = T(0);
   __syncthreads();
-  for (int qp = threadIdx.x; qp < Nq; qp += 256) {
-    T ep[6] = {0, 0, 0, 0, 0, 0};
-    for (int j = 0; j < Np; ++j) {
-      const T vv = VqT[j * Nq + qp];
-      for (int m = 0; m < 6; ++m) ep[m] += vv * se[m * Np + j];
+  acc_t pq[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) pq[m] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
+  for (int qc = 0; qc < NQC; ++qc) {
+    const int q0 = qc * QC;
+    const int rows = (NqK - q0) < QC ? (NqK - q0) : QC;
+    const int Rq = q0 / 16 + w;
+    if (w < QC / 16 && Rq < QT) {
+      const int64_t ge = e0 + lr < K ? e0 + lr : K - 1;
+      T lam[4], mu2[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int qp = Rq * 16 + M::row(lg, r);
+        const bool ok = qp < Nq && e0 + lr < K;
+        const int qq = qp < Nq ? qp : Nq - 1;
+        lam[r] = ok ? lm[ge * 2 * NqP + qq] : T(0);
+        mu2[r] = ok ? T(2) * lm[ge * 2 * NqP + NqP + qq] : T(0);
+      }
+      acc_t ac[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) ac[m] = acc_t{0, 0, 0, 0};
+      const T* Vr = Vqpad + (Rq * KD) * 64 + l;
+#pragma unroll 4
+      for (int kk = 0; kk < KD; ++kk) {
+        const T vf = Vr[kk * 64];
+        const int row = (4 * kk + lg) * SE + lr;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) ac[m] = M::mma(vf, Se[row + m * 16], ac[m]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int qp = Rq * 16 + M::row(lg, r);
+        if (qp >= NqK) continue;
+        T* o = &Sq[(qp - q0) * SQ + lr];
+        const T ltr = lam[r] * (ac[0][r] + ac[1][r] + ac[2][r]);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) o[m * 16] = mu2[r] * ac[m][r] + (m < 3 ? ltr : T(0));
+      }
     }
-    const T lam = lm[e * 2 * S::NqP + qp], mu = lm[e * 2 * S::NqP + S::NqP + qp];
-    const T ltr = lam * (ep[0] + ep[1] + ep[2]);
-    for (int m = 0; m < 6; ++m) sg[m * Nq + qp] = T(2) * mu * ep[m] + (m < 3 ? ltr : T(0));
+    __syncthreads();
+    if (w < RT) {
+      const T* Pr = Pqpad + (w * (NqK / 4) + q0 / 4) * 64 + l;
+#pragma unroll 4
+      for (int u = 0; u < QC / 4; ++u) {
+        if (4 * u < rows) {
+          const T pf = Pr[u * 64];
+          const int row = (4 * u + lg) * SQ + lr;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) pq[m] = M::mma(pf, Sq[row + m * 16], pq[m]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (w < RT) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = w * 16 + M::row(lg, r);
+      if (i < Np) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) Se[i * SE + m * 16 + lr] = pq[m][r];
+      }
+    }
   }
   __syncthreads();
-  for (int x = threadIdx.x; x < 6 * Np; x += 256) {
-    const int m = x / Np, i = x % Np;
-    T acc = 0;
-    for (int qp = 0; qp < Nq; ++qp) acc += PqT[qp * Np + i] * sg[m * Nq + qp];
-    s[e * 6 * Np + x] = acc;
+  for (int x = tid; x < E * 6 * Np; x += NT) {
+    const int e = x / (6 * Np), rem = x % (6 * Np), m = rem / Np, i = rem % Np;
+    if (e0 + e < K) s[(e0 + e) * 6 * Np + rem] = Se[i * SE + m * 16 + e];
   }
 }
 
@@ -1387,18 +1455,18 @@ hipError_t launch_rinv(const Dev& d, hipStream_t st) {
 }
 
 hipError_t launch_sigma(const Dev& d, const void* q, void* s, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(d.K));
+  const dim3 grid(static_cast<unsigned>((d.K + 15) / 16));
   if (d.prec == 32) {
-    EWDG_DISPATCH(d.N, hipLaunchKernelGGL((k_sigma<float, NN>), grid, dim3(256), 0, st,
+    EWDG_DISPATCH(d.N, hipLaunchKernelGGL((k_sigma<float, NN>), grid, dim3(Tile<NN>::NT), 0, st,
                                           static_cast<const float*>(q), static_cast<float*>(s),
-                                          static_cast<const float*>(d.lm), static_cast<const float*>(d.VqT),
-                                          static_cast<const float*>(d.PqT), d.K);
+                                          static_cast<const float*>(d.lm), static_cast<const float*>(d.Vqpad),
+                                          static_cast<const float*>(d.Pqpad), d.K);
                   return hipGetLastError());
   }
-  EWDG_DISPATCH(d.N, hipLaunchKernelGGL((k_sigma<double, NN>), grid, dim3(256), 0, st,
+  EWDG_DISPATCH(d.N, hipLaunchKernelGGL((k_sigma<double, NN>), grid, dim3(Tile<NN>::NT), 0, st,
                                         static_cast<const double*>(q), static_cast<double*>(s),
-                                        static_cast<const double*>(d.lm), static_cast<const double*>(d.VqT),
-                                        static_cast<const double*>(d.PqT), d.K);
+                                        static_cast<const double*>(d.lm), static_cast<const double*>(d.Vqpad),
+                                        static_cast<const double*>(d.Pqpad), d.K);
                 return hipGetLastError());
 }
 
