@@ -10,9 +10,10 @@
 //  EWDG_SV, EWDG_SE, EWDG_SF, EWDG_SQ: LDS row strides (values) of the 3-,
 //    6-, 9- and 6-field operand buffers, 16 element columns per field;
 //  EWDG_QC: quadrature points per projection chunk;
-//  EWDG_CW, EWDG_CW64: W_rho column values whose loads issue together (FP32;
-//    FP64 up to N = 4, where 12 to 24 measured alike and 1 % faster than 40,
-//    while N = 7 was 1 % slower with 20);
+//  EWDG_CW, EWDG_CW64: W_rho column values whose loads issue together (FP32,
+//    where N = 5 takes its whole row of 56 instead, 1.4 % faster; FP64 up to
+//    N = 4, where 12 to 24 measured alike and 1 % faster than 40, while N = 7
+//    was 1 % slower with 20);
 //  EWDG_OCC32: FP32 waves per SIMD asked of the register allocator.
 #ifndef EWDG_SV
 #define EWDG_SV 48
