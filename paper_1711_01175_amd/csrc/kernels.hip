@@ -579,7 +579,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& a, int tile) {
   };
   // one pair at a time, the W row in chunks of CW values whose loads issue
   // together (the rows of the larger degrees do not fit in the registers)
-  constexpr int CWP = sizeof(T) == 8 ? (N <= 4 ? EWDG_CW64 : EWDG_CW) : (N <= 5 && Np > EWDG_CW ? Np : EWDG_CW);
+  constexpr int CWP = sizeof(T) == 8 ? (N <= 4 ? EWDG_CW64 : EWDG_CW) : (N <= 5 ? Np : EWDG_CW32);
   constexpr int CW = Np < CWP ? Np : CWP;
 #pragma unroll
   for (int p = 0; p < NPU; ++p) {

@@ -10,10 +10,11 @@
 //  EWDG_SV, EWDG_SE, EWDG_SF, EWDG_SQ: LDS row strides (values) of the 3-,
 //    6-, 9- and 6-field operand buffers, 16 element columns per field;
 //  EWDG_QC: quadrature points per projection chunk;
-//  EWDG_CW, EWDG_CW64: W_rho column values whose loads issue together (FP32,
-//    where N = 5 takes its whole row of 56 instead, 1.4 % faster; FP64 up to
-//    N = 4, where 12 to 24 measured alike and 1 % faster than 40, while N = 7
-//    was 1 % slower with 20);
+//  EWDG_CW, EWDG_CW64, EWDG_CW32: W_rho column values whose loads issue
+//    together: FP64 at N >= 5 (40; 20 was 1 % slower at N = 7), FP64 up to
+//    N = 4 (20; 12 to 24 alike, 1 % faster than 40), FP32 at N = 7 (16; 12 to
+//    16 alike, 5 % faster than 40).  FP32 up to N = 5 takes the whole row
+//    (N = 5: 56 values, 1.4 % faster than 40);
 //  EWDG_OCC32: FP32 waves per SIMD asked of the register allocator.
 #ifndef EWDG_SV
 #define EWDG_SV 48
@@ -35,6 +36,9 @@
 #endif
 #ifndef EWDG_CW64
 #define EWDG_CW64 20
+#endif
+#ifndef EWDG_CW32
+#define EWDG_CW32 16
 #endif
 #ifndef EWDG_OCC32
 #define EWDG_OCC32 4
